@@ -1,0 +1,200 @@
+/*
+ * vecchia.h - C ABI of the MI355X (gfx950) Vecchia Gaussian log-CDF library.
+ *
+ * Method: Nascimento & Shaby, "A Vecchia Approximation for High-Dimensional
+ * Gaussian Cumulative Distribution Functions Arising from Spatial Data".
+ *   log F(x) ~= log Phi(x_1) + sum_{i>=2} [log Phi(x_{i,N_i}) - log Phi(x_{N_i})]
+ * (Section 2.2, eq. (6)), N_i = the min(m, i-1) nearest preceding locations
+ * (Section 2.1 after eq. (4)), each ratio estimated by Genz's separation of
+ * variables and a randomized rank-1 lattice QMC rule (Section 2.2 after eq.
+ * (6)), computed on the log scale and summed at the end (Section 3.1).
+ * The process is zero-mean with a stationary isotropic covariance; callers
+ * pass x - mu.
+ *
+ * Conventions for every entry point:
+ *  - No exception crosses the ABI. A non-OK status sets a thread-local message
+ *    readable with vecchia_last_error().
+ *  - "_host" pointers are host memory, "_dev" pointers are device memory of the
+ *    current HIP device. The caller owns both and every stream.
+ *  - Objects (plans, batches, servers) are owned by the library and released by
+ *    their _destroy call.
+ *  - Streams are hipStream_t passed as void* (NULL = the default stream).
+ *  - Calls that enqueue GPU work are asynchronous on the given stream; their
+ *    device outputs are valid once the stream reaches that point. A numerically
+ *    failed term (Cholesky pivot <= 0) makes the affected instance's outputs NaN
+ *    and is reported by vecchia_plan_status / vecchia_batch_status.
+ *  - Calls on one plan (or one batch) must be ordered on one stream at a time:
+ *    the plan's workspace is reused by every call.
+ */
+#ifndef VECCHIA_H
+#define VECCHIA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct vecchia_plan_s* vecchia_plan_t;
+typedef struct vecchia_batch_s* vecchia_batch_t;
+typedef struct vecchia_server_s* vecchia_server_t;
+
+typedef enum {
+  VECCHIA_OK = 0,
+  VECCHIA_E_INVALID = 1,     /* bad argument; nothing was enqueued                         */
+  VECCHIA_E_NOMEM = 2,       /* device or host allocation failed, or over the HBM budget    */
+  VECCHIA_E_NOT_PD = 3,      /* a term's covariance block is not positive definite          */
+  VECCHIA_E_HIP = 4,         /* a HIP runtime call failed                                   */
+  VECCHIA_E_BUSY = 5,        /* object still has requests in flight                         */
+  VECCHIA_E_NOT_READY = 6,   /* result not available yet                                    */
+  VECCHIA_E_NONFINITE = 7    /* non-finite input                                            */
+} vecchia_status;
+
+/* Orderings applied before neighbour selection (the paper orders components
+ * before choosing nearest neighbours, Section 3.2, and names no rule).
+ * COORD: lexicographic by (x, y, index). MAXMIN: first the point nearest the
+ * bounding-box centre, then repeatedly the point farthest from the selected
+ * set (ties: lowest index). GIVEN: a caller permutation. */
+enum { VECCHIA_ORDER_GIVEN = 0, VECCHIA_ORDER_COORD = 1, VECCHIA_ORDER_MAXMIN = 2 };
+
+/* Covariance families: exponential sigma2*exp(-h/range) (the paper's model,
+ * Sections 3 and 4.1) and Matern with nu in {0.5, 1.5, 2.5},
+ * K(h) = sigma2 2^(1-nu)/Gamma(nu) (sqrt(2 nu) h/range)^nu K_nu(sqrt(2 nu) h/range). */
+enum { VECCHIA_COV_EXPONENTIAL = 0, VECCHIA_COV_MATERN = 1 };
+
+/* Arithmetic of the QMC sample loop. FP64: every step in double precision.
+ * FP32_LOOP: the SOV chain (Phi, Phi^-1, products in log space) in single
+ * precision; covariance, Cholesky, per-term means and the sum in double. */
+enum { VECCHIA_FP64 = 0, VECCHIA_FP32_LOOP = 1 };
+
+#define VECCHIA_MAX_M 31          /* conditioning-set size limit (term dimension <= 32) */
+#define VECCHIA_MAX_SHIFTS 65536
+#define VECCHIA_MAX_POINTS 1073741824
+
+typedef struct {
+  int32_t family;   /* VECCHIA_COV_*                                  */
+  int32_t reserved; /* must be 0                                      */
+  double nu;        /* Matern smoothness: 0.5, 1.5 or 2.5             */
+  double sigma2;    /* marginal variance > 0                          */
+  double range;     /* range parameter > 0                            */
+  double nugget;    /* >= 0, added to the diagonal                    */
+} vecchia_cov;
+
+typedef struct {
+  int32_t n_points;   /* N lattice points per shift, 1..VECCHIA_MAX_POINTS          */
+  int32_t n_shifts;   /* R random shifts, 1..VECCHIA_MAX_SHIFTS (R = 1: SE is NaN)  */
+  uint64_t seed;      /* keys the random shifts                                     */
+  int32_t precision;  /* VECCHIA_FP64 or VECCHIA_FP32_LOOP                          */
+  int32_t reserved;   /* must be 0                                                  */
+} vecchia_qmc;
+
+/* Message for the calling thread's last non-OK status ("" if none). */
+const char* vecchia_last_error(void);
+
+/* Ordering only, on the host (no GPU work). locs_host: D x 2 row-major
+ * (x, y). perm_in_host: the permutation for VECCHIA_ORDER_GIVEN, else NULL.
+ * perm_out_host[i] = user index placed at plan position i (D entries).
+ * Errors: INVALID (D < 1, non-finite coordinates, bad ordering or permutation). */
+vecchia_status vecchia_order(const double* locs_host, int64_t D, int32_t ordering,
+                             const int64_t* perm_in_host, int64_t* perm_out_host);
+
+/* Build a plan: order the D locations, copy them to the device and find, with
+ * the GPU kernel knn_preceding, each component's min(m, i) nearest preceding
+ * neighbours under the (squared distance, plan index) order (Section 2.1).
+ * locs_host: D x dim row-major, dim must be 2. cov: default covariance; family
+ * and nu are fixed for the plan, sigma2/range/nugget may be overridden per
+ * call. Synchronises hip_stream before returning.
+ * Errors: INVALID (D < 1, D >= 2^31, dim != 2, m outside 0..31, bad ordering,
+ * permutation or covariance, non-finite locations), NOMEM, HIP. */
+vecchia_status vecchia_plan(const double* locs_host, int64_t D, int32_t dim, int32_t ordering,
+                            const int64_t* perm_in_host, int32_t m, const vecchia_cov* cov,
+                            void* hip_stream, vecchia_plan_t* out);
+
+/* Plan over an explicit D x D covariance (row-major, host, D <= 4096) with
+ * identity ordering; used to run closed-form cases through the same kernels.
+ * nbr_host: D x m row-major plan indices, each row listing its conditioning set
+ * (entries < i, distinct) first, padded with -1; NULL means the min(m, i)
+ * immediately preceding indices in ascending order.
+ * Errors: INVALID (bad sizes, non-finite or asymmetric matrix, bad lists),
+ * NOMEM, HIP. Synchronises hip_stream. */
+vecchia_status vecchia_plan_from_cov(const double* cov_host, int64_t D, const int32_t* nbr_host,
+                                     int32_t m, void* hip_stream, vecchia_plan_t* out);
+
+/* D and m of a plan. */
+vecchia_status vecchia_plan_info(vecchia_plan_t plan, int64_t* D, int32_t* m);
+
+/* Copy the plan's ordering and neighbour table to the host:
+ * perm_host[i] = user index at plan position i (D entries); nbr_host: D x m
+ * row-major plan indices, -1 padded (may be NULL when m = 0). Synchronous. */
+vecchia_status vecchia_plan_neighbours(vecchia_plan_t plan, int64_t* perm_host, int32_t* nbr_host);
+
+/* Vecchia log-CDF of one instance: log P(X < x / scale).
+ * x_dev: D doubles in user index order. scale > 0 divides the thresholds (the
+ * scale-mixture integrand Phi_D(x / r), eq. (9)). cov_override: NULL or a
+ * covariance with the plan's family and nu. q: QMC size, seed and precision.
+ * out_dev: 2 doubles, {log F, standard error}. terms_dev: NULL or D x 2
+ * doubles {log term, standard error} in user index order.
+ * Enqueues term_setup, the QMC kernels and finalize_logsum on hip_stream.
+ * Errors: INVALID (bad arguments; nothing enqueued), NOMEM, HIP. */
+vecchia_status vecchia_logcdf(vecchia_plan_t plan, const double* x_dev, double scale,
+                              const vecchia_cov* cov_override, const vecchia_qmc* q,
+                              double* out_dev, double* terms_dev, void* hip_stream);
+
+/* Wait for the plan's last call and report whether every term factored:
+ * OK, or NOT_PD with the first failing plan-order term in *bad_term
+ * (-1 when OK) and in the error message. */
+vecchia_status vecchia_plan_status(vecchia_plan_t plan, int64_t* bad_term);
+
+/* Release a plan. BUSY if server requests on it are still in flight. */
+vecchia_status vecchia_plan_destroy(vecchia_plan_t plan);
+
+/* A batch of n instances evaluated in one pass: one setup launch, one QMC
+ * launch per distinct conditioning-set size (largest first), one
+ * segmented-sum launch, replayed from a captured HIP graph after the first
+ * call. plans: n plans (may repeat). qmcs: n QMC settings (copied). */
+vecchia_status vecchia_batch_create(const vecchia_plan_t* plans, int32_t n, const vecchia_qmc* qmcs,
+                                    vecchia_batch_t* out);
+
+/* Evaluate a batch. x_dev: thresholds of all instances concatenated in batch
+ * order (sum of D doubles, each in its plan's user order). scales_host: n
+ * scales or NULL (all 1). covs_host: n covariances or NULL (each plan's own).
+ * out_dev: n x 2 doubles {log F, SE}. Errors: INVALID, NOMEM, HIP. */
+vecchia_status vecchia_batch_logcdf(vecchia_batch_t batch, const double* x_dev,
+                                    const double* scales_host, const vecchia_cov* covs_host,
+                                    double* out_dev, void* hip_stream);
+
+/* As vecchia_plan_status for every instance of the batch: bad_terms_host (n
+ * entries, may be NULL) receives -1 or the first failing plan-order term. */
+vecchia_status vecchia_batch_status(vecchia_batch_t batch, int64_t* bad_terms_host);
+
+vecchia_status vecchia_batch_destroy(vecchia_batch_t batch);
+
+/* Serving: a request loop with continuous batching. Requests are admitted in
+ * arrival order while their workspace fits in hbm_budget_bytes and one of
+ * max_slots execution slots (each its own stream) is free; admitted requests
+ * run concurrently on the device. A scheduler thread owns the GPU side.
+ * Errors: INVALID (budget 0, max_slots outside 1..64), NOMEM, HIP. */
+vecchia_status vecchia_server_create(size_t hbm_budget_bytes, int32_t max_slots, vecchia_server_t* out);
+
+/* Queue one log-CDF request; returns at once with a ticket. x_dev must stay
+ * valid and unchanged until the request is done. Errors: INVALID (bad
+ * arguments), NOMEM (the request alone exceeds the HBM budget). */
+vecchia_status vecchia_submit(vecchia_server_t server, vecchia_plan_t plan, const double* x_dev,
+                              double scale, const vecchia_cov* cov_override, const vecchia_qmc* q,
+                              uint64_t* ticket);
+
+/* Non-blocking. *done = 1 and {log F, SE} when finished (the ticket is then
+ * released), else *done = 0. latency_s (may be NULL): submit-to-completion
+ * seconds. Errors: INVALID (unknown ticket), NOT_PD (the request's covariance
+ * failed; the ticket is released). */
+vecchia_status vecchia_poll(vecchia_server_t server, uint64_t ticket, double* logF, double* se,
+                            int32_t* done, double* latency_s);
+
+/* Stop the scheduler after in-flight work drains and free the server. */
+vecchia_status vecchia_server_destroy(vecchia_server_t server);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VECCHIA_H */

@@ -1,0 +1,292 @@
+// C ABI entry points (include/vecchia.h): argument checks, plan construction
+// (host ordering + GPU nearest-neighbour kernel) and the evaluation calls.
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "host_order.h"
+#include "runtime.h"
+
+using namespace vecchia;
+
+namespace vecchia {
+const char* last_error_message();
+}
+
+namespace {
+
+template <class T>
+hipError_t dev_alloc(T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) return hipSuccess;
+  return hipMalloc(reinterpret_cast<void**>(p), sizeof(T) * count);
+}
+
+void free_plan_buffers(vecchia_plan_s* P) {
+  hipFree(P->d_xs);
+  hipFree(P->d_ys);
+  hipFree(P->d_cov);
+  hipFree(P->d_perm);
+  hipFree(P->d_nbr);
+  hipFree(P->d_kcnt);
+}
+
+vecchia_status order_impl(const double* locs, int64_t D, int32_t ordering, const int64_t* perm_in,
+                          int64_t* perm_out) {
+  if (!locs || !perm_out) return set_error(VECCHIA_E_INVALID, "null pointer");
+  if (D < 1 || D > 0x7fffffffLL) return set_error(VECCHIA_E_INVALID, "D must be in 1..2^31-1");
+  for (int64_t j = 0; j < 2 * D; ++j)
+    if (!std::isfinite(locs[j])) return set_error(VECCHIA_E_INVALID, "non-finite location");
+  switch (ordering) {
+    case VECCHIA_ORDER_COORD:
+      order_coord(locs, D, perm_out);
+      return VECCHIA_OK;
+    case VECCHIA_ORDER_MAXMIN:
+      order_maxmin(locs, D, perm_out);
+      return VECCHIA_OK;
+    case VECCHIA_ORDER_GIVEN: {
+      if (!perm_in) return set_error(VECCHIA_E_INVALID, "VECCHIA_ORDER_GIVEN needs a permutation");
+      std::vector<char> seen(D, 0);
+      for (int64_t i = 0; i < D; ++i) {
+        const int64_t v = perm_in[i];
+        if (v < 0 || v >= D || seen[v]) return set_error(VECCHIA_E_INVALID, "given ordering is not a permutation");
+        seen[v] = 1;
+        perm_out[i] = v;
+      }
+      return VECCHIA_OK;
+    }
+    default:
+      return set_error(VECCHIA_E_INVALID, "unknown ordering");
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* vecchia_last_error(void) { return last_error_message(); }
+
+vecchia_status vecchia_order(const double* locs_host, int64_t D, int32_t ordering,
+                             const int64_t* perm_in_host, int64_t* perm_out_host) {
+  return order_impl(locs_host, D, ordering, perm_in_host, perm_out_host);
+}
+
+vecchia_status vecchia_plan(const double* locs_host, int64_t D, int32_t dim, int32_t ordering,
+                            const int64_t* perm_in_host, int32_t m, const vecchia_cov* cov,
+                            void* hip_stream, vecchia_plan_t* out) {
+  if (!out || !cov) return set_error(VECCHIA_E_INVALID, "null pointer");
+  *out = nullptr;
+  if (dim != 2) return set_error(VECCHIA_E_INVALID, "only 2-D locations are supported (dim must be 2)");
+  if (m < 0 || m > VECCHIA_MAX_M) return set_error(VECCHIA_E_INVALID, "m must be in 0..31");
+  std::string why;
+  if (!valid_cov(*cov, &why)) return set_error(VECCHIA_E_INVALID, why);
+  std::vector<int64_t> perm(D > 0 && D <= 0x7fffffffLL ? D : 0);
+  vecchia_status st = order_impl(locs_host, D, ordering, perm_in_host, perm.data());
+  if (st != VECCHIA_OK) return st;
+  auto* P = new (std::nothrow) vecchia_plan_s();
+  if (!P) return set_error(VECCHIA_E_NOMEM, "host allocation");
+  hipGetDevice(&P->device);
+  P->D = D;
+  P->m = m;
+  P->cov = *cov;
+  P->perm = perm;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  std::vector<double> hx(D), hy(D);
+  std::vector<int32_t> hp(D);
+  for (int64_t i = 0; i < D; ++i) {
+    hx[i] = locs_host[2 * perm[i]];
+    hy[i] = locs_host[2 * perm[i] + 1];
+    hp[i] = (int32_t)perm[i];
+  }
+  hipError_t e = dev_alloc(&P->d_xs, D);
+  if (e == hipSuccess) e = dev_alloc(&P->d_ys, D);
+  if (e == hipSuccess) e = dev_alloc(&P->d_perm, D);
+  if (e == hipSuccess) e = dev_alloc(&P->d_kcnt, D);
+  if (e == hipSuccess && m > 0) e = dev_alloc(&P->d_nbr, (size_t)D * m);
+  if (e == hipSuccess) e = hipMemcpyAsync(P->d_xs, hx.data(), sizeof(double) * D, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(P->d_ys, hy.data(), sizeof(double) * D, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(P->d_perm, hp.data(), sizeof(int32_t) * D, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = launch_knn(P->d_xs, P->d_ys, D, m, P->d_nbr, P->d_kcnt, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e == hipSuccess) {
+    P->kcnt.resize(D);
+    e = hipMemcpy(P->kcnt.data(), P->d_kcnt, sizeof(int32_t) * D, hipMemcpyDeviceToHost);
+  }
+  if (e != hipSuccess) {
+    free_plan_buffers(P);
+    delete P;
+    return hip_error(e, "plan construction");
+  }
+  *out = P;
+  return VECCHIA_OK;
+}
+
+vecchia_status vecchia_plan_from_cov(const double* cov_host, int64_t D, const int32_t* nbr_host,
+                                     int32_t m, void* hip_stream, vecchia_plan_t* out) {
+  if (!out || !cov_host) return set_error(VECCHIA_E_INVALID, "null pointer");
+  *out = nullptr;
+  if (D < 1 || D > 4096) return set_error(VECCHIA_E_INVALID, "D must be in 1..4096");
+  if (m < 0 || m > VECCHIA_MAX_M) return set_error(VECCHIA_E_INVALID, "m must be in 0..31");
+  for (int64_t a = 0; a < D; ++a)
+    for (int64_t b = 0; b < D; ++b) {
+      const double v = cov_host[a * D + b];
+      if (!std::isfinite(v)) return set_error(VECCHIA_E_INVALID, "non-finite covariance entry");
+      if (v != cov_host[b * D + a]) return set_error(VECCHIA_E_INVALID, "covariance matrix is not symmetric");
+    }
+  std::vector<int32_t> nbr((size_t)D * m, -1), kc(D, 0);
+  for (int64_t i = 0; i < D; ++i) {
+    if (nbr_host) {
+      int k = 0;
+      while (k < m && nbr_host[i * m + k] >= 0) ++k;
+      for (int c = k; c < m; ++c)
+        if (nbr_host[i * m + c] != -1) return set_error(VECCHIA_E_INVALID, "neighbour rows must be -1 padded at the end");
+      for (int c = 0; c < k; ++c) {
+        const int32_t v = nbr_host[i * m + c];
+        if (v >= i) return set_error(VECCHIA_E_INVALID, "neighbour " + std::to_string(v) + " of row " + std::to_string(i) + " does not precede it");
+        for (int c2 = 0; c2 < c; ++c2)
+          if (nbr_host[i * m + c2] == v) return set_error(VECCHIA_E_INVALID, "repeated neighbour");
+        nbr[i * m + c] = v;
+      }
+      kc[i] = k;
+    } else {
+      const int k = (int)(i < m ? i : m);
+      for (int c = 0; c < k; ++c) nbr[i * m + c] = (int32_t)(i - k + c);
+      kc[i] = k;
+    }
+  }
+  auto* P = new (std::nothrow) vecchia_plan_s();
+  if (!P) return set_error(VECCHIA_E_NOMEM, "host allocation");
+  hipGetDevice(&P->device);
+  P->D = D;
+  P->m = m;
+  P->matrix = true;
+  P->cov = vecchia_cov{VECCHIA_COV_EXPONENTIAL, 0, 0.5, 1.0, 1.0, 0.0};
+  P->perm.resize(D);
+  P->kcnt = kc;
+  std::vector<int32_t> hp(D);
+  for (int64_t i = 0; i < D; ++i) {
+    P->perm[i] = i;
+    hp[i] = (int32_t)i;
+  }
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  hipError_t e = dev_alloc(&P->d_cov, (size_t)D * D);
+  if (e == hipSuccess) e = dev_alloc(&P->d_perm, D);
+  if (e == hipSuccess) e = dev_alloc(&P->d_kcnt, D);
+  if (e == hipSuccess && m > 0) e = dev_alloc(&P->d_nbr, (size_t)D * m);
+  if (e == hipSuccess) e = hipMemcpyAsync(P->d_cov, cov_host, sizeof(double) * D * D, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(P->d_perm, hp.data(), sizeof(int32_t) * D, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(P->d_kcnt, kc.data(), sizeof(int32_t) * D, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && m > 0)
+    e = hipMemcpyAsync(P->d_nbr, nbr.data(), sizeof(int32_t) * D * m, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    free_plan_buffers(P);
+    delete P;
+    return hip_error(e, "plan construction");
+  }
+  *out = P;
+  return VECCHIA_OK;
+}
+
+vecchia_status vecchia_plan_info(vecchia_plan_t plan, int64_t* D, int32_t* m) {
+  if (!plan) return set_error(VECCHIA_E_INVALID, "null plan");
+  if (D) *D = plan->D;
+  if (m) *m = plan->m;
+  return VECCHIA_OK;
+}
+
+vecchia_status vecchia_plan_neighbours(vecchia_plan_t plan, int64_t* perm_host, int32_t* nbr_host) {
+  if (!plan) return set_error(VECCHIA_E_INVALID, "null plan");
+  if (perm_host) std::memcpy(perm_host, plan->perm.data(), sizeof(int64_t) * plan->D);
+  if (nbr_host && plan->m > 0) {
+    hipError_t e = hipMemcpy(nbr_host, plan->d_nbr, sizeof(int32_t) * plan->D * plan->m, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_error(e, "neighbour copy");
+  }
+  return VECCHIA_OK;
+}
+
+vecchia_status vecchia_logcdf(vecchia_plan_t plan, const double* x_dev, double scale,
+                              const vecchia_cov* cov_override, const vecchia_qmc* q,
+                              double* out_dev, double* terms_dev, void* hip_stream) {
+  if (!plan || !q) return set_error(VECCHIA_E_INVALID, "null pointer");
+  std::string why;
+  if (!valid_qmc(*q, &why)) return set_error(VECCHIA_E_INVALID, why);
+  std::lock_guard<std::mutex> lk(plan->mu);
+  Batch* b = plan->single.get();
+  if (!b || b->qmcs()[0].n_shifts != q->n_shifts || b->qmcs()[0].precision != q->precision) {
+    std::unique_ptr<Batch> nb;
+    vecchia_status st = Batch::create({plan}, {*q}, &nb);
+    if (st != VECCHIA_OK) return st;
+    plan->single = std::move(nb);
+    b = plan->single.get();
+  }
+  const uint64_t seed = q->seed;
+  const int32_t np = q->n_points;
+  return b->run(x_dev, &scale, cov_override, out_dev, terms_dev, &seed, &np,
+                static_cast<hipStream_t>(hip_stream));
+}
+
+vecchia_status vecchia_plan_status(vecchia_plan_t plan, int64_t* bad_term) {
+  if (!plan) return set_error(VECCHIA_E_INVALID, "null plan");
+  if (bad_term) *bad_term = -1;
+  std::lock_guard<std::mutex> lk(plan->mu);
+  if (!plan->single) return VECCHIA_OK;
+  std::vector<int64_t> bad;
+  vecchia_status st = plan->single->status(&bad);
+  if (bad_term && !bad.empty()) *bad_term = bad[0];
+  return st;
+}
+
+vecchia_status vecchia_plan_destroy(vecchia_plan_t plan) {
+  if (!plan) return set_error(VECCHIA_E_INVALID, "null plan");
+  if (plan->inflight.load() > 0) return set_error(VECCHIA_E_BUSY, "plan has requests in flight");
+  if (plan->single && plan->single->last_stream() != nullptr) hipStreamSynchronize(plan->single->last_stream());
+  hipDeviceSynchronize();
+  plan->single.reset();
+  free_plan_buffers(plan);
+  delete plan;
+  return VECCHIA_OK;
+}
+
+vecchia_status vecchia_batch_create(const vecchia_plan_t* plans, int32_t n, const vecchia_qmc* qmcs,
+                                    vecchia_batch_t* out) {
+  if (!plans || !qmcs || !out || n < 1) return set_error(VECCHIA_E_INVALID, "bad batch arguments");
+  *out = nullptr;
+  std::vector<vecchia_plan_s*> ps(plans, plans + n);
+  std::vector<vecchia_qmc> qs(qmcs, qmcs + n);
+  std::unique_ptr<Batch> b;
+  vecchia_status st = Batch::create(ps, qs, &b);
+  if (st != VECCHIA_OK) return st;
+  auto* h = new (std::nothrow) vecchia_batch_s();
+  if (!h) return set_error(VECCHIA_E_NOMEM, "host allocation");
+  h->b = std::move(b);
+  *out = h;
+  return VECCHIA_OK;
+}
+
+vecchia_status vecchia_batch_logcdf(vecchia_batch_t batch, const double* x_dev, const double* scales_host,
+                                    const vecchia_cov* covs_host, double* out_dev, void* hip_stream) {
+  if (!batch) return set_error(VECCHIA_E_INVALID, "null batch");
+  return batch->b->run(x_dev, scales_host, covs_host, out_dev, nullptr, nullptr, nullptr,
+                       static_cast<hipStream_t>(hip_stream));
+}
+
+vecchia_status vecchia_batch_status(vecchia_batch_t batch, int64_t* bad_terms_host) {
+  if (!batch) return set_error(VECCHIA_E_INVALID, "null batch");
+  std::vector<int64_t> bad;
+  vecchia_status st = batch->b->status(&bad);
+  if (bad_terms_host) std::memcpy(bad_terms_host, bad.data(), sizeof(int64_t) * bad.size());
+  return st;
+}
+
+vecchia_status vecchia_batch_destroy(vecchia_batch_t batch) {
+  if (!batch) return set_error(VECCHIA_E_INVALID, "null batch");
+  if (batch->b && batch->b->last_stream() != nullptr) hipStreamSynchronize(batch->b->last_stream());
+  hipDeviceSynchronize();
+  delete batch;
+  return VECCHIA_OK;
+}
+
+}  // extern "C"

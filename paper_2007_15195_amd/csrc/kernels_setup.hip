@@ -1,0 +1,139 @@
+// term_setup: steps a2-a3 of every Vecchia term (Section 2.2, eq. (6)).
+//
+// One wave per term. The term's variables are its conditioning set N_i (in the
+// plan's (d^2, index) order) followed by i itself. The wave gathers their
+// locations and thresholds b = x / scale, builds the covariance block C in LDS
+// (FP64), factors C = L L^T in place (left-looking, one lane per row) and writes
+// the rows the SOV chain needs, scaled by the diagonal:
+//     row a (a = 0..k):  L_a0/L_aa, ..., L_a,a-1/L_aa, b_a/L_aa
+// at offset a(a+1)/2 of the term's block, so that t_a = b_a/L_aa - sum_c (L_ac/L_aa) y_c.
+// It also stores Phi(b_0/L_00), the exact value of a term with k = 0.
+// A pivot <= 0 (or NaN) marks the term NOT_PD: its outputs become NaN and the
+// instance's bad_term is lowered to i.
+#include "vecchia_internal.h"
+
+namespace vecchia {
+namespace {
+
+__device__ double cov_kernel(double h, int family, double nu, double s2, double rho) {
+#pragma clang fp contract(off)
+  if (family == VECCHIA_COV_EXPONENTIAL || nu == 0.5) return s2 * exp(-h / rho);
+  if (nu == 1.5) {
+    const double a = 1.7320508075688772 * h / rho;   // sqrt(3) h / rho
+    return s2 * (1.0 + a) * exp(-a);
+  }
+  const double a = 2.23606797749979 * h / rho;       // sqrt(5) h / rho
+  return s2 * (1.0 + a + a * a / 3.0) * exp(-a);
+}
+
+__device__ __forceinline__ int find_inst(const int64_t* __restrict__ bases, int n, int64_t t) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (bases[mid] <= t) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(64) void term_setup(const InstDesc* __restrict__ insts, int n_inst,
+                                                 const int64_t* __restrict__ term_bases,
+                                                 Aux64* __restrict__ aux64,
+                                                 Aux32* __restrict__ aux32) {
+  __shared__ double C[kMaxVars][kMaxVars + 1];
+  __shared__ double px[kMaxVars], py[kMaxVars], pb[kMaxVars];
+  __shared__ int pv[kMaxVars];
+  __shared__ double piv;
+  const int lane = threadIdx.x;
+  const int64_t t = blockIdx.x;
+  const int ii = find_inst(term_bases, n_inst, t);
+  const InstDesc& I = insts[ii];
+  const int64_t i = t - term_bases[ii];
+  const int k = I.kcnt[i];
+  const int n = k + 1;
+  if (lane < n) {
+    const int64_t v = lane < k ? (int64_t)I.nbr[i * I.m + lane] : i;
+    pv[lane] = (int)v;
+    if (!I.covmat) {
+      px[lane] = I.xs[v];
+      py[lane] = I.ys[v];
+    }
+    pb[lane] = I.x[I.perm[v]] * I.inv_scale;
+  }
+  __syncthreads();
+  for (int idx = lane; idx < n * n; idx += 64) {
+    const int a = idx / n;
+    const int c = idx - a * n;
+    if (c > a) continue;
+    double cv;
+    if (I.covmat) {
+      cv = I.covmat[(int64_t)pv[a] * I.D + pv[c]];
+    } else {
+#pragma clang fp contract(off)
+      const double dx = px[a] - px[c];
+      const double dy = py[a] - py[c];
+      cv = cov_kernel(sqrt(dx * dx + dy * dy), I.family, I.nu, I.sigma2, I.range);
+      if (a == c) cv += I.nugget;
+    }
+    C[a][c] = cv;
+  }
+  __syncthreads();
+  bool bad = false;
+  for (int j = 0; j < n; ++j) {
+    double s = 0.0;
+    if (lane >= j && lane < n) {
+      s = C[lane][j];
+      for (int p = 0; p < j; ++p) s -= C[lane][p] * C[j][p];
+    }
+    if (lane == j) piv = s;
+    __syncthreads();
+    const double d = piv;
+    if (!(d > 0.0)) bad = true;
+    const double ljj = sqrt(d);
+    if (lane > j && lane < n) C[lane][j] = s / ljj;
+    if (lane == j) C[j][j] = ljj;
+    __syncthreads();
+  }
+  const double nan = __builtin_nan("");
+  const bool f32 = I.precision == VECCHIA_FP32_LOOP;
+  if (lane < n) {
+    const double laa = C[lane][lane];
+    const int64_t off = i * (int64_t)I.prep_stride + (int64_t)lane * (lane + 1) / 2;
+    if (f32) {
+      float* row = reinterpret_cast<float*>(I.prep) + off;
+      for (int c = 0; c < lane; ++c) row[c] = (float)(C[lane][c] / laa);
+      row[lane] = bad ? __builtin_nanf("") : (float)(pb[lane] / laa);
+    } else {
+      double* row = reinterpret_cast<double*>(I.prep) + off;
+      for (int c = 0; c < lane; ++c) row[c] = C[lane][c] / laa;
+      row[lane] = bad ? nan : pb[lane] / laa;
+    }
+  }
+  if (lane == 0) {
+    const double b0 = pb[0] / C[0][0];
+    const double e0 = bad ? nan : normcdf(b0);
+    aux64[t].e0 = e0;
+    aux64[t].lt0 = bad ? nan : log(e0);
+    if (f32) {
+      Aux32 a;
+      a.e0 = (float)e0;
+      a.ec0 = bad ? __builtin_nanf("") : (float)normcdf(-b0);
+      a.le0 = (float)log(e0);
+      a.pad = 0.0f;
+      aux32[t] = a;
+    }
+    if (bad) atomicMin((long long*)I.bad_term, (long long)i);
+  }
+}
+
+}  // namespace
+
+hipError_t launch_setup(const InstDesc* d_insts, int n_inst, const int64_t* d_term_bases,
+                        int64_t total_terms, Aux64* aux64, Aux32* aux32, hipStream_t s) {
+  if (total_terms <= 0) return hipSuccess;
+  if (total_terms > 0x7fffffffLL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(term_setup, dim3((unsigned)total_terms), dim3(64), 0, s, d_insts, n_inst,
+                     d_term_bases, aux64, aux32);
+  return hipGetLastError();
+}
+
+}  // namespace vecchia

@@ -1,0 +1,433 @@
+// Host runtime: error state, lattice table, and the Batch engine that lays out
+// and enqueues one evaluation (setup -> QMC per conditioning-set size, largest
+// first -> segmented sum), optionally replayed from a captured HIP graph.
+#include "runtime.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+
+namespace vecchia {
+
+namespace {
+thread_local std::string g_err;
+std::mutex g_dev_mu;
+std::map<int, uint64_t*> g_Z;
+
+// floor(frac(sqrt(p)) * 2^64) for a non-square p < 2^32, by bisection on the
+// exact condition (f 2^64 + Z)^2 <= p 2^128 with f = floor(sqrt(p)), i.e.
+// Z^2 + 2 f Z 2^64 <= (p - f^2) 2^128, evaluated in three 64-bit limbs.
+uint64_t frac_sqrt_fixed(uint64_t p) {
+  uint64_t f = 0;
+  while ((f + 1) * (f + 1) <= p) ++f;
+  const uint64_t c = p - f * f;
+  auto fits = [&](uint64_t Z) {
+    const unsigned __int128 zz = (unsigned __int128)Z * Z;
+    const unsigned __int128 fz = (unsigned __int128)(2 * f) * Z;   // < 2^70
+    const uint64_t l1a = (uint64_t)(zz >> 64);
+    const uint64_t l1b = (uint64_t)fz;
+    const uint64_t l1 = l1a + l1b;
+    const uint64_t carry = l1 < l1a;
+    const unsigned __int128 l2 = (unsigned __int128)(uint64_t)(fz >> 64) + carry;
+    (void)l1;
+    return l2 < c || (l2 == c && l1 == 0 && (uint64_t)zz == 0);
+  };
+  uint64_t Z = 0;
+  for (int b = 63; b >= 0; --b) {
+    const uint64_t cand = Z | (1ULL << b);
+    if (fits(cand)) Z = cand;
+  }
+  return Z;
+}
+}  // namespace
+
+vecchia_status set_error(vecchia_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+vecchia_status hip_error(hipError_t e, const char* what) {
+  return set_error(e == hipErrorOutOfMemory ? VECCHIA_E_NOMEM : VECCHIA_E_HIP,
+                   std::string(what) + ": " + hipGetErrorString(e));
+}
+
+const char* last_error_message() { return g_err.c_str(); }
+
+const uint64_t* device_lattice_table(int device, hipError_t* err) {
+  std::lock_guard<std::mutex> lk(g_dev_mu);
+  auto it = g_Z.find(device);
+  if (it != g_Z.end()) {
+    *err = hipSuccess;
+    return it->second;
+  }
+  uint64_t Z[kMaxM];
+  int found = 0;
+  for (uint64_t c = 2; found < kMaxM; ++c) {
+    bool prime = true;
+    for (uint64_t d = 2; d * d <= c; ++d)
+      if (c % d == 0) { prime = false; break; }
+    if (prime) Z[found++] = frac_sqrt_fixed(c);
+  }
+  uint64_t* d = nullptr;
+  *err = hipMalloc(&d, sizeof(Z));
+  if (*err != hipSuccess) return nullptr;
+  *err = hipMemcpy(d, Z, sizeof(Z), hipMemcpyHostToDevice);
+  if (*err != hipSuccess) return nullptr;
+  g_Z[device] = d;
+  return d;
+}
+
+bool valid_cov(const vecchia_cov& c, std::string* why) {
+  if (c.family != VECCHIA_COV_EXPONENTIAL && c.family != VECCHIA_COV_MATERN) {
+    *why = "unknown covariance family";
+    return false;
+  }
+  if (c.family == VECCHIA_COV_MATERN && !(c.nu == 0.5 || c.nu == 1.5 || c.nu == 2.5)) {
+    *why = "Matern nu must be 0.5, 1.5 or 2.5";
+    return false;
+  }
+  if (!(std::isfinite(c.sigma2) && c.sigma2 > 0)) { *why = "sigma2 must be finite and > 0"; return false; }
+  if (!(std::isfinite(c.range) && c.range > 0)) { *why = "range must be finite and > 0"; return false; }
+  if (!(std::isfinite(c.nugget) && c.nugget >= 0)) { *why = "nugget must be finite and >= 0"; return false; }
+  return true;
+}
+
+bool valid_qmc(const vecchia_qmc& q, std::string* why) {
+  if (q.n_points < 1 || q.n_points > VECCHIA_MAX_POINTS) { *why = "n_points out of range"; return false; }
+  if (q.n_shifts < 1 || q.n_shifts > VECCHIA_MAX_SHIFTS) { *why = "n_shifts out of range"; return false; }
+  if (q.precision != VECCHIA_FP64 && q.precision != VECCHIA_FP32_LOOP) {
+    *why = "precision must be VECCHIA_FP64 or VECCHIA_FP32_LOOP";
+    return false;
+  }
+  return true;
+}
+
+// ------------------------------------------------------------------ Batch ---
+
+Batch::~Batch() {
+  if (graph_exec_) hipGraphExecDestroy(graph_exec_);
+  for (auto& e : stage_ev_)
+    if (e) hipEventDestroy(e);
+  if (done_ev_) hipEventDestroy(done_ev_);
+  if (h_stage_) hipHostFree(h_stage_);
+  if (d_ws_) hipFree(d_ws_);
+}
+
+static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+vecchia_status Batch::create(const std::vector<vecchia_plan_s*>& plans,
+                             const std::vector<vecchia_qmc>& qmcs, std::unique_ptr<Batch>* out) {
+  if (plans.empty() || plans.size() != qmcs.size())
+    return set_error(VECCHIA_E_INVALID, "batch needs n >= 1 plans and as many qmc settings");
+  if (plans.size() > 0x7fffffff) return set_error(VECCHIA_E_INVALID, "too many instances");
+  std::unique_ptr<Batch> b(new Batch());
+  b->plans_ = plans;
+  b->qmcs_ = qmcs;
+  int dev = 0;
+  hipGetDevice(&dev);
+  b->device_ = dev;
+  const int n = (int)plans.size();
+  b->term_bases_.resize(n + 1);
+  b->desc_.resize(n);
+  b->prep_off_.resize(n);
+  int64_t tb = 0, sb = 0;
+  size_t prep = 0;
+  std::map<std::pair<int, int>, std::vector<RangeDesc>> by_k;   // (K, precision) -> ranges
+  for (int j = 0; j < n; ++j) {
+    vecchia_plan_s* P = plans[j];
+    std::string why;
+    if (!P) return set_error(VECCHIA_E_INVALID, "null plan in batch");
+    if (P->device != dev) return set_error(VECCHIA_E_INVALID, "plan belongs to another device");
+    if (!valid_qmc(qmcs[j], &why)) return set_error(VECCHIA_E_INVALID, "instance " + std::to_string(j) + ": " + why);
+    const int R = qmcs[j].n_shifts;
+    const int prec = qmcs[j].precision;
+    const int nv = P->m + 1;
+    const int stride = (int)align_up((size_t)nv * (nv + 1) / 2, prec == VECCHIA_FP32_LOOP ? 4 : 2);
+    InstDesc& d = b->desc_[j];
+    std::memset(&d, 0, sizeof(d));
+    d.xs = P->d_xs;
+    d.ys = P->d_ys;
+    d.covmat = P->d_cov;
+    d.perm = P->d_perm;
+    d.nbr = P->d_nbr;
+    d.kcnt = P->d_kcnt;
+    d.D = P->D;
+    d.term_base = tb;
+    d.sums_base = sb;
+    d.m = P->m;
+    d.n_points = qmcs[j].n_points;
+    d.n_shifts = R;
+    d.seed = qmcs[j].seed;
+    d.prep_stride = stride;
+    d.precision = prec;
+    b->term_bases_[j] = tb;
+    b->prep_off_[j] = prep;
+    prep += align_up((size_t)P->D * stride * (prec == VECCHIA_FP32_LOOP ? 4 : 8), 256);
+    if (prec == VECCHIA_FP32_LOOP) b->any_f32_ = true;
+    // runs of equal k >= 1 become ranges of the launch for that k
+    int64_t i = 0;
+    while (i < P->D) {
+      const int k = P->kcnt[i];
+      int64_t e = i + 1;
+      while (e < P->D && P->kcnt[e] == k) ++e;
+      if (k >= 1) {
+        RangeDesc r;
+        r.item_begin = e - i;   // term count; turned into the item prefix below
+        r.term_begin = i;
+        r.inst = j;
+        r.n_shifts = R;
+        by_k[{k, prec}].push_back(r);
+      }
+      i = e;
+    }
+    tb += P->D;
+    sb += P->D * (int64_t)R;
+  }
+  b->term_bases_[n] = tb;
+  b->total_terms_ = tb;
+  b->total_sums_ = sb;
+  b->prep_bytes_ = prep;
+  if (tb > 0x7fffffffLL) return set_error(VECCHIA_E_INVALID, "more than 2^31-1 terms in one batch");
+  // launches: largest K first
+  for (auto it = by_k.rbegin(); it != by_k.rend(); ++it) {
+    Launch L;
+    L.K = it->first.first;
+    L.precision = it->first.second;
+    L.range_off = (int)b->ranges_.size();
+    L.n_ranges = (int)it->second.size();
+    int64_t items = 0;
+    for (RangeDesc r : it->second) {
+      const int64_t nterms = r.item_begin;
+      r.item_begin = items;
+      items += nterms * r.n_shifts;
+      b->ranges_.push_back(r);
+    }
+    L.n_items = items;
+    b->launches_.push_back(L);
+  }
+  // workspace layout
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off = align_up(off + bytes, 256);
+    return at;
+  };
+  take(sizeof(InstDesc) * n);
+  take(sizeof(int64_t) * (n + 1));
+  take(sizeof(RangeDesc) * std::max<size_t>(1, b->ranges_.size()));
+  take(sizeof(Aux64) * tb);
+  if (b->any_f32_) take(sizeof(Aux32) * tb);
+  take(sizeof(double) * 3 * sb);
+  take(sizeof(int64_t) * n);
+  take(prep);
+  b->ws_bytes_ = off;
+  *out = std::move(b);
+  return VECCHIA_OK;
+}
+
+vecchia_status Batch::allocate() {
+  if (d_ws_ || d_desc_) return VECCHIA_OK;
+  hipError_t e;
+  d_Z_ = device_lattice_table(device_, &e);
+  if (!d_Z_) return hip_error(e, "lattice table");
+  char* base = ext_ws_;
+  if (!base) {
+    e = hipMalloc(&d_ws_, ws_bytes_);
+    if (e != hipSuccess) {
+      d_ws_ = nullptr;
+      return hip_error(e, "workspace allocation");
+    }
+    base = d_ws_;
+  }
+  const int n = (int)plans_.size();
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    char* p = base + off;
+    off = align_up(off + bytes, 256);
+    return p;
+  };
+  d_desc_ = reinterpret_cast<InstDesc*>(take(sizeof(InstDesc) * n));
+  d_term_bases_ = reinterpret_cast<int64_t*>(take(sizeof(int64_t) * (n + 1)));
+  d_ranges_ = reinterpret_cast<RangeDesc*>(take(sizeof(RangeDesc) * std::max<size_t>(1, ranges_.size())));
+  d_aux64_ = reinterpret_cast<Aux64*>(take(sizeof(Aux64) * total_terms_));
+  if (any_f32_) d_aux32_ = reinterpret_cast<Aux32*>(take(sizeof(Aux32) * total_terms_));
+  d_sums_ = reinterpret_cast<double*>(take(sizeof(double) * 3 * total_sums_));
+  d_bad_ = reinterpret_cast<int64_t*>(take(sizeof(int64_t) * n));
+  d_prep_ = take(prep_bytes_);
+  for (int j = 0; j < n; ++j) {
+    desc_[j].prep = d_prep_ + prep_off_[j];
+    desc_[j].bad_term = d_bad_ + j;
+  }
+  if (!ext_stage_) {
+    e = hipHostMalloc(reinterpret_cast<void**>(&h_stage_), sizeof(InstDesc) * n * kRing, hipHostMallocDefault);
+    if (e != hipSuccess) {
+      h_stage_ = nullptr;
+      return hip_error(e, "pinned staging");
+    }
+    for (auto& ev : stage_ev_) {
+      e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+      if (e != hipSuccess) return hip_error(e, "event");
+    }
+  }
+  e = hipEventCreateWithFlags(&done_ev_, hipEventDisableTiming);
+  if (e != hipSuccess) return hip_error(e, "event");
+  return VECCHIA_OK;
+}
+
+vecchia_status Batch::enqueue(hipStream_t s) {
+  const int n = (int)plans_.size();
+  hipError_t e = launch_fill_i64(d_bad_, n, INT64_MAX, s);
+  if (e == hipSuccess)
+    e = launch_setup(d_desc_, n, d_term_bases_, total_terms_, d_aux64_, d_aux32_, s);
+  for (const Launch& L : launches_) {
+    if (e != hipSuccess) break;
+    e = launch_qmc(L.K, L.precision, d_desc_, d_ranges_ + L.range_off, L.n_ranges, L.n_items,
+                   d_aux64_, d_aux32_, d_Z_, d_sums_, s);
+  }
+  if (e == hipSuccess) e = launch_finalize(d_desc_, n, d_aux64_, d_sums_, s);
+  if (e != hipSuccess) return hip_error(e, "kernel launch");
+  return VECCHIA_OK;
+}
+
+vecchia_status Batch::run(const double* x_dev, const double* scales, const vecchia_cov* covs,
+                          double* out_dev, double* terms_dev, const uint64_t* seeds,
+                          const int32_t* n_points, hipStream_t s) {
+  const int n = (int)plans_.size();
+  if (!x_dev || !out_dev) return set_error(VECCHIA_E_INVALID, "x_dev and out_dev must be device pointers");
+  int dev = 0;
+  hipGetDevice(&dev);
+  if (dev != device_) return set_error(VECCHIA_E_INVALID, "current device differs from the batch's device");
+  // device buffers first: the descriptors below carry their addresses
+  vecchia_status st = allocate();
+  if (st != VECCHIA_OK) return st;
+  int64_t xo = 0;
+  std::vector<InstDesc> d = desc_;
+  for (int j = 0; j < n; ++j) {
+    vecchia_plan_s* P = plans_[j];
+    const vecchia_cov c = covs ? covs[j] : P->cov;
+    std::string why;
+    if (covs) {
+      if (!valid_cov(c, &why)) return set_error(VECCHIA_E_INVALID, "instance " + std::to_string(j) + ": " + why);
+      if (!P->matrix && (c.family != P->cov.family || (c.family == VECCHIA_COV_MATERN && c.nu != P->cov.nu)))
+        return set_error(VECCHIA_E_INVALID, "covariance override must keep the plan's family and nu");
+    }
+    const double sc = scales ? scales[j] : 1.0;
+    if (!(std::isfinite(sc) && sc > 0)) return set_error(VECCHIA_E_INVALID, "scale must be finite and > 0");
+    if (n_points && (n_points[j] < 1 || n_points[j] > VECCHIA_MAX_POINTS))
+      return set_error(VECCHIA_E_INVALID, "n_points out of range");
+    d[j].x = x_dev + xo;
+    d[j].out = out_dev + 2 * j;
+    d[j].terms_out = terms_dev;
+    d[j].inv_scale = 1.0 / sc;
+    d[j].family = c.family;
+    d[j].nu = c.family == VECCHIA_COV_EXPONENTIAL ? 0.5 : c.nu;
+    d[j].sigma2 = c.sigma2;
+    d[j].range = c.range;
+    d[j].nugget = c.nugget;
+    if (seeds) d[j].seed = seeds[j];
+    if (n_points) d[j].n_points = n_points[j];
+    xo += P->D;
+  }
+  if (n > 1 && terms_dev) return set_error(VECCHIA_E_INVALID, "per-term output is for single instances");
+  for (int j = 0; j < n; ++j) {
+    // every address a kernel dereferences must be set before anything is enqueued
+    const InstDesc& q = d[j];
+    const bool geom_ok = q.covmat || (q.xs && q.ys);
+    if (!q.prep || !q.bad_term || !q.x || !q.out || !q.kcnt || !q.perm || !geom_ok ||
+        (q.m > 0 && !q.nbr) || !d_desc_ || !d_term_bases_ || !d_ranges_ || !d_aux64_ || !d_sums_ ||
+        !d_Z_ || (any_f32_ && !d_aux32_))
+      return set_error(VECCHIA_E_HIP, "internal error: incomplete device descriptor");
+  }
+  hipError_t e = hipSuccess;
+  if (!tables_uploaded_) {
+    // host tables live as long as the batch, so the asynchronous copy is safe
+    e = hipMemcpyAsync(d_term_bases_, term_bases_.data(), sizeof(int64_t) * (n + 1),
+                       hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && !ranges_.empty())
+      e = hipMemcpyAsync(d_ranges_, ranges_.data(), sizeof(RangeDesc) * ranges_.size(),
+                         hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_error(e, "batch tables");
+    tables_uploaded_ = true;
+  }
+  // stage the descriptors in pinned memory no earlier copy still reads
+  InstDesc* h = ext_stage_;
+  int slot = -1;
+  if (!h) {
+    slot = stage_next_;
+    stage_next_ = (stage_next_ + 1) % kRing;
+    if (stage_used_[slot]) e = hipEventSynchronize(stage_ev_[slot]);
+    if (e != hipSuccess) return hip_error(e, "staging wait");
+    h = h_stage_ + (size_t)slot * n;
+  }
+  std::memcpy(h, d.data(), sizeof(InstDesc) * n);
+  e = hipMemcpyAsync(d_desc_, h, sizeof(InstDesc) * n, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && slot >= 0) e = hipEventRecord(stage_ev_[slot], s);
+  if (e != hipSuccess) return hip_error(e, "descriptor copy");
+  if (slot >= 0) stage_used_[slot] = true;
+
+  static const bool no_graph = std::getenv("VECCHIA_NO_GRAPH") != nullptr;
+  const bool use_graph = !no_graph && !graph_failed_ && s != nullptr && eager_runs_ >= 1 && !ext_stage_;
+  if (use_graph) {
+    if (graph_exec_ && graph_stream_ != s) {
+      // graphs are replayed on the stream they were captured for
+      hipGraphExecDestroy(graph_exec_);
+      graph_exec_ = nullptr;
+    }
+    if (!graph_exec_) {
+      hipGraph_t g = nullptr;
+      e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+      if (e == hipSuccess) {
+        st = enqueue(s);
+        hipError_t e2 = hipStreamEndCapture(s, &g);
+        if (st == VECCHIA_OK && e2 == hipSuccess && g) {
+          e2 = hipGraphInstantiate(&graph_exec_, g, nullptr, nullptr, 0);
+          if (e2 != hipSuccess) graph_exec_ = nullptr;
+        }
+        if (g) hipGraphDestroy(g);
+        if (!graph_exec_) graph_failed_ = true;
+      } else {
+        graph_failed_ = true;
+      }
+      hipGetLastError();
+      graph_stream_ = s;
+    }
+  }
+  if (graph_exec_ && use_graph) {
+    e = hipGraphLaunch(graph_exec_, s);
+    if (e != hipSuccess) return hip_error(e, "graph launch");
+  } else {
+    st = enqueue(s);
+    if (st != VECCHIA_OK) return st;
+    ++eager_runs_;
+  }
+  e = hipEventRecord(done_ev_, s);
+  if (e != hipSuccess) return hip_error(e, "event record");
+  last_stream_ = s;
+  ran_ = true;
+  return VECCHIA_OK;
+}
+
+vecchia_status Batch::status(std::vector<int64_t>* bad) {
+  const int n = (int)plans_.size();
+  bad->assign(n, -1);
+  if (!ran_) return VECCHIA_OK;
+  hipError_t e = hipEventSynchronize(done_ev_);
+  if (e != hipSuccess) return hip_error(e, "wait");
+  std::vector<int64_t> h(n);
+  e = hipMemcpy(h.data(), d_bad_, sizeof(int64_t) * n, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_error(e, "status copy");
+  vecchia_status st = VECCHIA_OK;
+  for (int j = 0; j < n; ++j) {
+    if (h[j] != INT64_MAX) {
+      (*bad)[j] = h[j];
+      if (st == VECCHIA_OK)
+        st = set_error(VECCHIA_E_NOT_PD, "instance " + std::to_string(j) + ": covariance block of plan term " +
+                                             std::to_string(h[j]) + " is not positive definite");
+    }
+  }
+  return st;
+}
+
+}  // namespace vecchia

@@ -1,0 +1,128 @@
+// Host runtime objects behind the C ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cstdint>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "vecchia_internal.h"
+
+struct vecchia_plan_s;
+
+namespace vecchia {
+
+vecchia_status set_error(vecchia_status st, const std::string& msg);
+vecchia_status hip_error(hipError_t e, const char* what);
+const uint64_t* device_lattice_table(int device, hipError_t* err);
+bool valid_cov(const vecchia_cov& c, std::string* why);
+bool valid_qmc(const vecchia_qmc& q, std::string* why);
+
+// Everything one evaluation of a fixed set of instances needs on the device.
+class Batch {
+ public:
+  ~Batch();
+  // Validates and lays out the workspace; allocates nothing yet.
+  static vecchia_status create(const std::vector<vecchia_plan_s*>& plans,
+                               const std::vector<vecchia_qmc>& qmcs, std::unique_ptr<Batch>* out);
+  // Bytes of device memory run() needs (workspace + descriptors).
+  size_t workspace_bytes() const { return ws_bytes_; }
+  vecchia_status run(const double* x_dev, const double* scales, const vecchia_cov* covs,
+                     double* out_dev, double* terms_dev, const uint64_t* seeds,
+                     const int32_t* n_points, hipStream_t s);
+  vecchia_status status(std::vector<int64_t>* bad);  // waits for the last run
+  // Run on caller-owned memory instead of allocating: ws (workspace_bytes(),
+  // 256-byte aligned, device) and stage (n() descriptors, pinned host, not
+  // reused by the caller before this batch's work has been consumed).
+  void bind_external(char* ws, InstDesc* stage) {
+    ext_ws_ = ws;
+    ext_stage_ = stage;
+  }
+  const int64_t* device_bad_terms() const { return d_bad_; }
+  int n() const { return (int)plans_.size(); }
+  const std::vector<vecchia_qmc>& qmcs() const { return qmcs_; }
+  hipStream_t last_stream() const { return last_stream_; }
+
+ private:
+  struct Launch {
+    int K;
+    int precision;
+    int range_off;
+    int n_ranges;
+    int64_t n_items;
+  };
+  vecchia_status allocate();
+  vecchia_status enqueue(hipStream_t s);
+
+  std::vector<vecchia_plan_s*> plans_;
+  std::vector<vecchia_qmc> qmcs_;
+  std::vector<InstDesc> desc_;          // host template of the descriptors
+  std::vector<int64_t> term_bases_;     // n + 1
+  std::vector<RangeDesc> ranges_;
+  std::vector<Launch> launches_;
+  std::vector<size_t> prep_off_;        // byte offset of each instance's prep block
+  int64_t total_terms_ = 0;
+  int64_t total_sums_ = 0;              // triples
+  size_t prep_bytes_ = 0;
+  bool any_f32_ = false;
+  size_t ws_bytes_ = 0;
+  int device_ = 0;
+
+  char* d_ws_ = nullptr;
+  InstDesc* d_desc_ = nullptr;
+  int64_t* d_term_bases_ = nullptr;
+  RangeDesc* d_ranges_ = nullptr;
+  Aux64* d_aux64_ = nullptr;
+  Aux32* d_aux32_ = nullptr;
+  double* d_sums_ = nullptr;
+  int64_t* d_bad_ = nullptr;
+  char* d_prep_ = nullptr;
+  const uint64_t* d_Z_ = nullptr;
+
+  static constexpr int kRing = 4;       // pinned descriptor staging slots
+  InstDesc* h_stage_ = nullptr;
+  hipEvent_t stage_ev_[kRing] = {};
+  bool stage_used_[kRing] = {};
+  int stage_next_ = 0;
+
+  hipEvent_t done_ev_ = nullptr;
+  hipStream_t last_stream_ = nullptr;
+  bool ran_ = false;
+
+  char* ext_ws_ = nullptr;
+  InstDesc* ext_stage_ = nullptr;
+  bool tables_uploaded_ = false;
+
+  hipGraphExec_t graph_exec_ = nullptr;
+  hipStream_t graph_stream_ = nullptr;
+  bool graph_failed_ = false;
+  int eager_runs_ = 0;
+};
+
+}  // namespace vecchia
+
+struct vecchia_plan_s {
+  int device = 0;
+  int64_t D = 0;
+  int32_t m = 0;
+  vecchia_cov cov{};
+  bool matrix = false;
+  std::vector<int64_t> perm;       // plan position -> user index
+  std::vector<int32_t> kcnt;       // host copy of k_i
+  double* d_xs = nullptr;
+  double* d_ys = nullptr;
+  double* d_cov = nullptr;
+  int32_t* d_perm = nullptr;
+  int32_t* d_nbr = nullptr;
+  int32_t* d_kcnt = nullptr;
+  std::unique_ptr<vecchia::Batch> single;   // cached one-instance batch of vecchia_logcdf
+  std::atomic<int> inflight{0};
+  std::mutex mu;
+};
+
+struct vecchia_batch_s {
+  std::unique_ptr<vecchia::Batch> b;
+};

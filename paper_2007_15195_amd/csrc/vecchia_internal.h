@@ -1,0 +1,67 @@
+// Internal types shared by the host runtime and the gfx950 kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "../../include/vecchia.h"
+
+namespace vecchia {
+
+constexpr int kMaxM = VECCHIA_MAX_M;   // conditioning-set size limit
+constexpr int kMaxVars = kMaxM + 1;    // variables per term
+constexpr int kQmcWaves = 4;           // waves (work items) per QMC block
+constexpr int kSetupTermsPerBlock = 4; // one wave per term in the setup kernel
+constexpr int kFinalizeThreads = 256;
+
+// One log-CDF instance of a launch (device-resident descriptor).
+struct InstDesc {
+  const double* xs;        // plan-order x coordinates (geometry plans)
+  const double* ys;        // plan-order y coordinates
+  const double* covmat;    // explicit D x D covariance (matrix plans) or null
+  const int32_t* perm;     // plan position -> user index
+  const int32_t* nbr;      // D x m conditioning sets (plan indices), -1 padded
+  const int32_t* kcnt;     // D: size k_i of each conditioning set
+  const double* x;         // thresholds, user order
+  double* out;             // {log F, SE}
+  double* terms_out;       // D x 2 user order, or null
+  void* prep;              // per-term scaled Cholesky rows (double or float), term 0
+  int64_t D;
+  int64_t term_base;       // global index of plan term 0 (aux arrays)
+  int64_t sums_base;       // index of (term 0, shift 0) in the sums triples
+  int64_t* bad_term;       // first plan-order term whose Cholesky failed (min)
+  double inv_scale, sigma2, range, nugget, nu;
+  int32_t family;          // VECCHIA_COV_*
+  int32_t m;
+  int32_t n_points, n_shifts;
+  uint64_t seed;
+  int32_t prep_stride;     // elements per term in prep
+  int32_t precision;       // VECCHIA_FP64 / VECCHIA_FP32_LOOP
+};
+
+// A contiguous run of terms with the same k inside one instance; its QMC work
+// items are (term, shift) pairs, n_terms * n_shifts of them.
+struct RangeDesc {
+  int64_t item_begin;      // exclusive prefix of items over the ranges of a launch
+  int64_t term_begin;      // plan index of the first term
+  int32_t inst;            // instance index
+  int32_t n_shifts;
+};
+
+// Auxiliary per-term values written by term_setup.
+struct Aux64 { double e0; double lt0; };                  // Phi(b_0/L_00), its log
+struct Aux32 { float e0, ec0, le0, pad; };                 // FP32 e0, 1-e0, log e0
+
+// Launchers (kernels_*.hip).
+hipError_t launch_knn(const double* xs, const double* ys, int64_t D, int m, int32_t* nbr,
+                      int32_t* kcnt, hipStream_t s);
+hipError_t launch_fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t s);
+hipError_t launch_setup(const InstDesc* d_insts, int n_inst, const int64_t* d_term_bases,
+                        int64_t total_terms, Aux64* aux64, Aux32* aux32, hipStream_t s);
+hipError_t launch_qmc(int K, int precision, const InstDesc* d_insts, const RangeDesc* d_ranges,
+                      int n_ranges, int64_t n_items, const Aux64* aux64, const Aux32* aux32,
+                      const uint64_t* d_Z, double* sums, hipStream_t s);
+hipError_t launch_finalize(const InstDesc* d_insts, int n_inst, const Aux64* aux64,
+                           const double* sums, hipStream_t s);
+
+}  // namespace vecchia

@@ -1,0 +1,276 @@
+"""ctypes binding of libvecchia.so, with the C ABI's names (include/vecchia.h).
+
+Argument marshalling only: every step of the method runs in the HIP library.
+Device buffers are torch CUDA tensors (float64); streams are torch.cuda
+streams or raw hipStream_t integers. Host arrays are numpy arrays. A non-OK
+status raises VecchiaError carrying the status and the library's message.
+The library must have been built (python -m paper_2007_15195_amd.build); there
+is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, byref, c_double, c_int32, c_int64, c_size_t, c_uint64, c_void_p
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "libvecchia.so")
+
+VECCHIA_OK = 0
+STATUS_NAMES = {0: "OK", 1: "E_INVALID", 2: "E_NOMEM", 3: "E_NOT_PD", 4: "E_HIP", 5: "E_BUSY",
+                6: "E_NOT_READY", 7: "E_NONFINITE"}
+VECCHIA_ORDER_GIVEN, VECCHIA_ORDER_COORD, VECCHIA_ORDER_MAXMIN = 0, 1, 2
+VECCHIA_COV_EXPONENTIAL, VECCHIA_COV_MATERN = 0, 1
+VECCHIA_FP64, VECCHIA_FP32_LOOP = 0, 1
+VECCHIA_MAX_M = 31
+
+EXPORTED = [
+    "vecchia_last_error", "vecchia_order", "vecchia_plan", "vecchia_plan_from_cov",
+    "vecchia_plan_info", "vecchia_plan_neighbours", "vecchia_logcdf", "vecchia_plan_status",
+    "vecchia_plan_destroy", "vecchia_batch_create", "vecchia_batch_logcdf", "vecchia_batch_status",
+    "vecchia_batch_destroy", "vecchia_server_create", "vecchia_submit", "vecchia_poll",
+    "vecchia_server_destroy",
+]
+
+
+class VecchiaError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class vecchia_cov(ctypes.Structure):
+    _fields_ = [("family", c_int32), ("reserved", c_int32), ("nu", c_double), ("sigma2", c_double),
+                ("range", c_double), ("nugget", c_double)]
+
+
+class vecchia_qmc(ctypes.Structure):
+    _fields_ = [("n_points", c_int32), ("n_shifts", c_int32), ("seed", c_uint64),
+                ("precision", c_int32), ("reserved", c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libvecchia.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2007_15195_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    L.vecchia_last_error.restype = ctypes.c_char_p
+    sig = {
+        "vecchia_order": [c_void_p, c_int64, c_int32, c_void_p, c_void_p],
+        "vecchia_plan": [c_void_p, c_int64, c_int32, c_int32, c_void_p, c_int32, POINTER(vecchia_cov),
+                         c_void_p, POINTER(c_void_p)],
+        "vecchia_plan_from_cov": [c_void_p, c_int64, c_void_p, c_int32, c_void_p, POINTER(c_void_p)],
+        "vecchia_plan_info": [c_void_p, POINTER(c_int64), POINTER(c_int32)],
+        "vecchia_plan_neighbours": [c_void_p, c_void_p, c_void_p],
+        "vecchia_logcdf": [c_void_p, c_void_p, c_double, c_void_p, POINTER(vecchia_qmc), c_void_p,
+                           c_void_p, c_void_p],
+        "vecchia_plan_status": [c_void_p, POINTER(c_int64)],
+        "vecchia_plan_destroy": [c_void_p],
+        "vecchia_batch_create": [c_void_p, c_int32, c_void_p, POINTER(c_void_p)],
+        "vecchia_batch_logcdf": [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p],
+        "vecchia_batch_status": [c_void_p, c_void_p],
+        "vecchia_batch_destroy": [c_void_p],
+        "vecchia_server_create": [c_size_t, c_int32, POINTER(c_void_p)],
+        "vecchia_submit": [c_void_p, c_void_p, c_void_p, c_double, c_void_p, POINTER(vecchia_qmc),
+                           POINTER(c_uint64)],
+        "vecchia_poll": [c_void_p, c_uint64, POINTER(c_double), POINTER(c_double), POINTER(c_int32),
+                         POINTER(c_double)],
+        "vecchia_server_destroy": [c_void_p],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = c_int32
+    _lib = L
+    return L
+
+
+def _check(status: int):
+    if status != VECCHIA_OK:
+        raise VecchiaError(status, lib().vecchia_last_error().decode())
+
+
+def _stream_ptr(stream) -> int:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _dev_ptr(t, n: int | None = None, name: str = "tensor") -> int:
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous float64 CUDA tensor")
+    if n is not None and t.numel() < n:
+        raise ValueError(f"{name} must hold at least {n} values")
+    return t.data_ptr()
+
+
+def make_cov(family=VECCHIA_COV_MATERN, nu=0.5, sigma2=1.0, range=0.1, nugget=0.0) -> vecchia_cov:
+    return vecchia_cov(int(family), 0, float(nu), float(sigma2), float(range), float(nugget))
+
+
+def make_qmc(n_points=1000, n_shifts=10, seed=1, precision=VECCHIA_FP64) -> vecchia_qmc:
+    return vecchia_qmc(int(n_points), int(n_shifts), int(seed) & (2 ** 64 - 1), int(precision), 0)
+
+
+def as_cov(c) -> vecchia_cov:
+    if c is None or isinstance(c, vecchia_cov):
+        return c
+    return make_cov(c.family, c.nu, c.sigma2, c.range, c.nugget)
+
+
+def as_qmc(q) -> vecchia_qmc:
+    if isinstance(q, vecchia_qmc):
+        return q
+    return make_qmc(q.n_points, q.n_shifts, q.seed, q.precision)
+
+
+# ----------------------------------------------------------------- entry points
+
+def vecchia_last_error() -> str:
+    return lib().vecchia_last_error().decode()
+
+
+def vecchia_order(locs: np.ndarray, ordering: int, perm=None) -> np.ndarray:
+    locs = np.ascontiguousarray(locs, dtype=np.float64)
+    D = locs.shape[0]
+    out = np.empty(D, dtype=np.int64)
+    pin = None if perm is None else np.ascontiguousarray(perm, dtype=np.int64)
+    _check(lib().vecchia_order(locs.ctypes.data, D, int(ordering),
+                               None if pin is None else pin.ctypes.data, out.ctypes.data))
+    return out
+
+
+def vecchia_plan(locs: np.ndarray, ordering: int, m: int, cov, perm=None, stream=None) -> int:
+    locs = np.ascontiguousarray(locs, dtype=np.float64)
+    if locs.ndim != 2:
+        raise ValueError("locs must be D x dim")
+    pin = None if perm is None else np.ascontiguousarray(perm, dtype=np.int64)
+    h = c_void_p()
+    c = as_cov(cov)
+    _check(lib().vecchia_plan(locs.ctypes.data, locs.shape[0], locs.shape[1], int(ordering),
+                              None if pin is None else pin.ctypes.data, int(m), byref(c),
+                              _stream_ptr(stream), byref(h)))
+    return h.value
+
+
+def vecchia_plan_from_cov(Sigma: np.ndarray, m: int, nbr=None, stream=None) -> int:
+    Sigma = np.ascontiguousarray(Sigma, dtype=np.float64)
+    D = Sigma.shape[0]
+    nb = None
+    if nbr is not None:
+        nb = np.full((D, m), -1, dtype=np.int32)
+        for i, row in enumerate(nbr):
+            row = list(row)
+            nb[i, :len(row)] = row
+    h = c_void_p()
+    _check(lib().vecchia_plan_from_cov(Sigma.ctypes.data, D, None if nb is None else nb.ctypes.data,
+                                       int(m), _stream_ptr(stream), byref(h)))
+    return h.value
+
+
+def vecchia_plan_info(plan: int):
+    D = c_int64()
+    m = c_int32()
+    _check(lib().vecchia_plan_info(plan, byref(D), byref(m)))
+    return D.value, m.value
+
+
+def vecchia_plan_neighbours(plan: int):
+    D, m = vecchia_plan_info(plan)
+    perm = np.empty(D, dtype=np.int64)
+    nbr = np.empty((D, max(m, 1)), dtype=np.int32)
+    _check(lib().vecchia_plan_neighbours(plan, perm.ctypes.data, nbr.ctypes.data if m > 0 else None))
+    return perm, nbr[:, :m]
+
+
+def vecchia_logcdf(plan: int, x, qmc, out, scale: float = 1.0, cov_override=None, terms=None,
+                   stream=None) -> None:
+    D, _ = vecchia_plan_info(plan)
+    q = as_qmc(qmc)
+    c = as_cov(cov_override)
+    _check(lib().vecchia_logcdf(plan, _dev_ptr(x, D, "x"), float(scale),
+                                None if c is None else ctypes.addressof(c), byref(q),
+                                _dev_ptr(out, 2, "out"),
+                                None if terms is None else _dev_ptr(terms, 2 * D, "terms"),
+                                _stream_ptr(stream)))
+
+
+def vecchia_plan_status(plan: int) -> int:
+    bad = c_int64(-1)
+    st = lib().vecchia_plan_status(plan, byref(bad))
+    if st not in (VECCHIA_OK, 3):
+        _check(st)
+    return bad.value
+
+
+def vecchia_plan_destroy(plan: int) -> None:
+    _check(lib().vecchia_plan_destroy(plan))
+
+
+def vecchia_batch_create(plans, qmcs) -> int:
+    n = len(plans)
+    arr = (c_void_p * n)(*plans)
+    qa = (vecchia_qmc * n)(*[as_qmc(q) for q in qmcs])
+    h = c_void_p()
+    _check(lib().vecchia_batch_create(ctypes.addressof(arr), n, ctypes.addressof(qa), byref(h)))
+    return h.value
+
+
+def vecchia_batch_logcdf(batch: int, x, out, scales=None, covs=None, stream=None) -> None:
+    sc = None if scales is None else np.ascontiguousarray(scales, dtype=np.float64)
+    ca = None if covs is None else (vecchia_cov * len(covs))(*[as_cov(c) for c in covs])
+    _check(lib().vecchia_batch_logcdf(batch, _dev_ptr(x, None, "x"),
+                                      None if sc is None else sc.ctypes.data,
+                                      None if ca is None else ctypes.addressof(ca),
+                                      _dev_ptr(out, None, "out"), _stream_ptr(stream)))
+
+
+def vecchia_batch_status(batch: int, n: int) -> np.ndarray:
+    bad = np.empty(n, dtype=np.int64)
+    st = lib().vecchia_batch_status(batch, bad.ctypes.data)
+    if st not in (VECCHIA_OK, 3):
+        _check(st)
+    return bad
+
+
+def vecchia_batch_destroy(batch: int) -> None:
+    _check(lib().vecchia_batch_destroy(batch))
+
+
+def vecchia_server_create(hbm_budget_bytes: int, max_slots: int) -> int:
+    h = c_void_p()
+    _check(lib().vecchia_server_create(int(hbm_budget_bytes), int(max_slots), byref(h)))
+    return h.value
+
+
+def vecchia_submit(server: int, plan: int, x, qmc, scale: float = 1.0, cov_override=None) -> int:
+    D, _ = vecchia_plan_info(plan)
+    q = as_qmc(qmc)
+    c = as_cov(cov_override)
+    t = c_uint64()
+    _check(lib().vecchia_submit(server, plan, _dev_ptr(x, D, "x"), float(scale),
+                                None if c is None else ctypes.addressof(c), byref(q), byref(t)))
+    return t.value
+
+
+def vecchia_poll(server: int, ticket: int):
+    """Returns None while running, else (logF, se, latency_s)."""
+    lf, se, lat = c_double(), c_double(), c_double()
+    done = c_int32()
+    _check(lib().vecchia_poll(server, ticket, byref(lf), byref(se), byref(done), byref(lat)))
+    return (lf.value, se.value, lat.value) if done.value else None
+
+
+def vecchia_server_destroy(server: int) -> None:
+    _check(lib().vecchia_server_destroy(server))

@@ -1,0 +1,94 @@
+"""CPU checks of the C ABI: the library loads, exports every entry point the
+header declares, orders locations on the host exactly as the oracle does, and
+rejects bad arguments before touching a GPU."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import ordering as oracle_ordering
+from paper_2007_15195_amd import vecchia as V
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "vecchia.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:vecchia_status|const char\*)\s+(vecchia_\w+)\s*\(", src, re.M)))
+
+
+def test_library_exports_every_declared_entry_point():
+    L = V.lib()
+    names = _declared()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(V.EXPORTED) == names
+
+
+def test_struct_layouts_match_header():
+    assert ctypes.sizeof(V.vecchia_cov) == 40
+    assert ctypes.sizeof(V.vecchia_qmc) == 24
+
+
+@pytest.mark.parametrize("rule", [W.ORDER_COORD, W.ORDER_MAXMIN])
+@pytest.mark.parametrize("case", ["grid", "uniform", "dupes", "line"])
+def test_host_ordering_matches_oracle(rule, case):
+    rng = np.random.default_rng(11)
+    if case == "grid":
+        locs = W.grid_locations(17, 13)
+    elif case == "uniform":
+        locs = rng.random((3000, 2))
+    elif case == "dupes":
+        locs = np.round(rng.random((500, 2)) * 6) / 6.0
+    else:
+        locs = np.stack([np.linspace(0, 1, 300), np.full(300, 0.25)], axis=1)
+    got = V.vecchia_order(locs, rule)
+    want = oracle_ordering.order(locs, rule)
+    assert np.array_equal(got, want)
+
+
+def test_host_maxmin_on_the_2500_point_workload():
+    inst = W.uniform2500_matern15()
+    assert np.array_equal(V.vecchia_order(inst.locs, W.ORDER_MAXMIN),
+                          oracle_ordering.maxmin_order(inst.locs))
+
+
+def test_given_ordering_and_validation():
+    locs = np.random.default_rng(1).random((5, 2))
+    assert list(V.vecchia_order(locs, W.ORDER_GIVEN, [4, 3, 2, 1, 0])) == [4, 3, 2, 1, 0]
+    with pytest.raises(V.VecchiaError) as e:
+        V.vecchia_order(locs, W.ORDER_GIVEN, [0, 0, 1, 2, 3])
+    assert e.value.status == 1
+    bad = locs.copy()
+    bad[2, 1] = np.nan
+    with pytest.raises(V.VecchiaError):
+        V.vecchia_order(bad, W.ORDER_COORD)
+    with pytest.raises(V.VecchiaError):
+        V.vecchia_order(locs, 7)
+
+
+def test_plan_rejects_bad_arguments_before_gpu_work():
+    locs = np.random.default_rng(1).random((5, 2))
+    cov = V.make_cov(V.VECCHIA_COV_MATERN, 1.5, 1.0, 0.1, 0.0)
+    for kwargs in (dict(m=32), dict(m=-1)):
+        with pytest.raises(V.VecchiaError) as e:
+            V.vecchia_plan(locs, W.ORDER_COORD, kwargs["m"], cov, stream=0)
+        assert e.value.status == 1
+    with pytest.raises(V.VecchiaError):
+        V.vecchia_plan(np.random.default_rng(1).random((5, 3)), W.ORDER_COORD, 2, cov, stream=0)
+    with pytest.raises(V.VecchiaError):
+        V.vecchia_plan(locs, W.ORDER_COORD, 2, V.make_cov(V.VECCHIA_COV_MATERN, 0.7, 1.0, 0.1), stream=0)
+    with pytest.raises(V.VecchiaError):
+        V.vecchia_plan(locs, W.ORDER_COORD, 2, V.make_cov(V.VECCHIA_COV_MATERN, 1.5, -1.0, 0.1), stream=0)
+    with pytest.raises(V.VecchiaError):
+        V.vecchia_plan_from_cov(np.array([[1.0, 0.5], [0.4, 1.0]]), 1, stream=0)   # not symmetric
+    with pytest.raises(V.VecchiaError):
+        V.vecchia_plan_from_cov(np.eye(3), 2, nbr=[[], [0], [2]], stream=0)      # not preceding
+    with pytest.raises(V.VecchiaError) as e:
+        V.vecchia_server_create(0, 4)
+    assert e.value.status == 1
+    assert "budget" in V.vecchia_last_error()
