@@ -121,6 +121,15 @@ vecchia_status vecchia_plan(const double* locs_host, int64_t D, int32_t dim, int
 vecchia_status vecchia_plan_from_cov(const double* cov_host, int64_t D, const int32_t* nbr_host,
                                      int32_t m, void* hip_stream, vecchia_plan_t* out);
 
+/* Recompute a geometry plan in place for new locations (same D, m and
+ * covariance family): host ordering, then an asynchronous copy and the
+ * knn_preceding kernel on hip_stream. Allocates nothing; the host ordering of
+ * this call overlaps GPU work already queued. Must be ordered with the plan's
+ * other calls on one stream. locs_host / perm_in_host as in vecchia_plan.
+ * Errors: INVALID (matrix plan, bad arguments), HIP. */
+vecchia_status vecchia_replan(vecchia_plan_t plan, const double* locs_host, int32_t ordering,
+                              const int64_t* perm_in_host, void* hip_stream);
+
 /* D and m of a plan. */
 vecchia_status vecchia_plan_info(vecchia_plan_t plan, int64_t* D, int32_t* m);
 
@@ -150,9 +159,11 @@ vecchia_status vecchia_plan_status(vecchia_plan_t plan, int64_t* bad_term);
 vecchia_status vecchia_plan_destroy(vecchia_plan_t plan);
 
 /* A batch of n instances evaluated in one pass: one setup launch, one QMC
- * launch per distinct conditioning-set size (largest first), one
- * segmented-sum launch, replayed from a captured HIP graph after the first
- * call. plans: n plans (may repeat). qmcs: n QMC settings (copied). */
+ * launch per distinct (conditioning-set size, precision) - the largest on the
+ * caller's stream, the others on library-owned side streams running beside it -
+ * and one segmented-sum launch, replayed from a captured HIP graph after the
+ * first call on a non-default stream. plans: n plans (may repeat). qmcs: n QMC
+ * settings (copied). */
 vecchia_status vecchia_batch_create(const vecchia_plan_t* plans, int32_t n, const vecchia_qmc* qmcs,
                                     vecchia_batch_t* out);
 
@@ -169,6 +180,17 @@ vecchia_status vecchia_batch_logcdf(vecchia_batch_t batch, const double* x_dev,
 vecchia_status vecchia_batch_status(vecchia_batch_t batch, int64_t* bad_terms_host);
 
 vecchia_status vecchia_batch_destroy(vecchia_batch_t batch);
+
+/* Kernel timing for measurement tools. While enabled, evaluations record HIP
+ * events around every QMC launch on its stream (HIP graphs are then not used).
+ * A QMC launch covers the terms of one conditioning-set size K in one
+ * precision. vecchia_profile_read waits for the recorded launches of (K,
+ * precision) and returns their summed milliseconds, launch count and SOV steps
+ * (sum over their terms of n_shifts * n_points * K). reset drops the records. */
+vecchia_status vecchia_profile_enable(int32_t on);
+vecchia_status vecchia_profile_read(int32_t K, int32_t precision, double* total_ms, int64_t* launches,
+                                    int64_t* sov_steps);
+vecchia_status vecchia_profile_reset(void);
 
 /* Serving: a request loop with continuous batching. Requests are admitted in
  * arrival order while their workspace fits in hbm_budget_bytes and one of

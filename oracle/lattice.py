@@ -15,7 +15,9 @@ definition produces the same bits):
 * Baker (tent) transform: W = |2U - 2^64| (W = 2^64 saturates to 2^64 - 1).
 * FP64 coordinate: the midpoint of the 2^-52 cell holding W / 2^64,
   w = (2 * floor(W / 2^12) + 1) * 2^-53, so 2^-53 <= w <= 1 - 2^-53 exactly.
-* FP32 coordinate: the midpoint of the 2^-23 cell, w = (2 * floor(W / 2^41) + 1) * 2^-24.
+* FP32 coordinate, from the upper 32 bits of U only: s = floor(U / 2^32) - 2^31
+  as a signed integer, c = |s| >> 8 for s >= 0 and (|s| - 1) >> 8 for s < 0,
+  w = (c + 1/2) 2^-23; within 2^-24 of the FP64 coordinate.
 """
 from __future__ import annotations
 
@@ -88,9 +90,10 @@ def coord_f64(W: np.ndarray) -> np.ndarray:
     return (2.0 * n + 1.0) * 2.0 ** -53
 
 
-def coord_f32(W: np.ndarray) -> np.ndarray:
-    n = (np.asarray(W, dtype=np.uint64) >> np.uint64(41)).astype(np.float64)
-    return (2.0 * n + 1.0) * 2.0 ** -24
+def coord_f32_from_u(U: np.ndarray) -> np.ndarray:
+    s = (np.asarray(U, dtype=np.uint64) >> np.uint64(32)).astype(np.int64) - (1 << 31)
+    c = np.where(s >= 0, s >> 8, (-s - 1) >> 8).astype(np.float64)
+    return (c + 0.5) * 2.0 ** -23
 
 
 def points(n_points: int, dim: int, S: int, Z: list | None = None,
@@ -98,5 +101,5 @@ def points(n_points: int, dim: int, S: int, Z: list | None = None,
     """Coordinates w_p (p = 1..N) of dimension `dim` for shift S."""
     Z = richtmyer_generator() if Z is None else Z
     p = np.arange(1, n_points + 1, dtype=np.uint64)
-    W = baker_w(lattice_u(p, Z[dim], S))
-    return coord_f32(W) if fp32 else coord_f64(W)
+    U = lattice_u(p, Z[dim], S)
+    return coord_f32_from_u(U) if fp32 else coord_f64(baker_w(U))

@@ -25,6 +25,10 @@ hipError_t dev_alloc(T** p, size_t count) {
 }
 
 void free_plan_buffers(vecchia_plan_s* P) {
+  for (int k = 0; k < 2; ++k) {
+    if (P->replan_ev[k]) hipEventDestroy(P->replan_ev[k]);
+    if (P->h_replan[k]) hipHostFree(P->h_replan[k]);
+  }
   hipFree(P->d_xs);
   hipFree(P->d_ys);
   hipFree(P->d_cov);
@@ -114,6 +118,11 @@ vecchia_status vecchia_plan(const double* locs_host, int64_t D, int32_t dim, int
     P->kcnt.resize(D);
     e = hipMemcpy(P->kcnt.data(), P->d_kcnt, sizeof(int32_t) * D, hipMemcpyDeviceToHost);
   }
+  for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+    e = hipHostMalloc(reinterpret_cast<void**>(&P->h_replan[k]), (2 * sizeof(double) + sizeof(int32_t)) * D,
+                      hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&P->replan_ev[k], hipEventDisableTiming);
+  }
   if (e != hipSuccess) {
     free_plan_buffers(P);
     delete P;
@@ -190,6 +199,41 @@ vecchia_status vecchia_plan_from_cov(const double* cov_host, int64_t D, const in
   return VECCHIA_OK;
 }
 
+vecchia_status vecchia_replan(vecchia_plan_t plan, const double* locs_host, int32_t ordering,
+                              const int64_t* perm_in_host, void* hip_stream) {
+  if (!plan) return set_error(VECCHIA_E_INVALID, "null plan");
+  if (plan->matrix) return set_error(VECCHIA_E_INVALID, "a matrix plan has no locations to re-plan");
+  std::lock_guard<std::mutex> lk(plan->mu);
+  if (plan->inflight.load() > 0) return set_error(VECCHIA_E_BUSY, "plan has requests in flight");
+  const int64_t D = plan->D;
+  std::vector<int64_t> perm(D);
+  vecchia_status st = order_impl(locs_host, D, ordering, perm_in_host, perm.data());
+  if (st != VECCHIA_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  const int k = plan->replan_next;
+  plan->replan_next ^= 1;
+  hipError_t e = hipSuccess;
+  if (plan->replan_used[k]) e = hipEventSynchronize(plan->replan_ev[k]);
+  if (e != hipSuccess) return hip_error(e, "replan staging wait");
+  double* hx = reinterpret_cast<double*>(plan->h_replan[k]);
+  double* hy = hx + D;
+  int32_t* hp = reinterpret_cast<int32_t*>(hy + D);
+  for (int64_t i = 0; i < D; ++i) {
+    hx[i] = locs_host[2 * perm[i]];
+    hy[i] = locs_host[2 * perm[i] + 1];
+    hp[i] = (int32_t)perm[i];
+  }
+  e = hipMemcpyAsync(plan->d_xs, hx, sizeof(double) * D, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(plan->d_ys, hy, sizeof(double) * D, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(plan->d_perm, hp, sizeof(int32_t) * D, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipEventRecord(plan->replan_ev[k], s);
+  if (e == hipSuccess) e = launch_knn(plan->d_xs, plan->d_ys, D, plan->m, plan->d_nbr, plan->d_kcnt, s);
+  if (e != hipSuccess) return hip_error(e, "replan");
+  plan->replan_used[k] = true;
+  plan->perm = std::move(perm);   // k_i = min(m, i) is unchanged
+  return VECCHIA_OK;
+}
+
 vecchia_status vecchia_plan_info(vecchia_plan_t plan, int64_t* D, int32_t* m) {
   if (!plan) return set_error(VECCHIA_E_INVALID, "null plan");
   if (D) *D = plan->D;
@@ -215,7 +259,8 @@ vecchia_status vecchia_logcdf(vecchia_plan_t plan, const double* x_dev, double s
   if (!valid_qmc(*q, &why)) return set_error(VECCHIA_E_INVALID, why);
   std::lock_guard<std::mutex> lk(plan->mu);
   Batch* b = plan->single.get();
-  if (!b || b->qmcs()[0].n_shifts != q->n_shifts || b->qmcs()[0].precision != q->precision) {
+  if (!b || b->qmcs()[0].n_shifts != q->n_shifts || b->qmcs()[0].precision != q->precision ||
+      b->qmcs()[0].n_points != q->n_points) {
     std::unique_ptr<Batch> nb;
     vecchia_status st = Batch::create({plan}, {*q}, &nb);
     if (st != VECCHIA_OK) return st;
@@ -223,9 +268,7 @@ vecchia_status vecchia_logcdf(vecchia_plan_t plan, const double* x_dev, double s
     b = plan->single.get();
   }
   const uint64_t seed = q->seed;
-  const int32_t np = q->n_points;
-  return b->run(x_dev, &scale, cov_override, out_dev, terms_dev, &seed, &np,
-                static_cast<hipStream_t>(hip_stream));
+  return b->run(x_dev, &scale, cov_override, out_dev, terms_dev, &seed, static_cast<hipStream_t>(hip_stream));
 }
 
 vecchia_status vecchia_plan_status(vecchia_plan_t plan, int64_t* bad_term) {
@@ -269,7 +312,7 @@ vecchia_status vecchia_batch_create(const vecchia_plan_t* plans, int32_t n, cons
 vecchia_status vecchia_batch_logcdf(vecchia_batch_t batch, const double* x_dev, const double* scales_host,
                                     const vecchia_cov* covs_host, double* out_dev, void* hip_stream) {
   if (!batch) return set_error(VECCHIA_E_INVALID, "null batch");
-  return batch->b->run(x_dev, scales_host, covs_host, out_dev, nullptr, nullptr, nullptr,
+  return batch->b->run(x_dev, scales_host, covs_host, out_dev, nullptr, nullptr,
                        static_cast<hipStream_t>(hip_stream));
 }
 

@@ -1,15 +1,19 @@
-// Single-precision normal CDF pieces for the SOV loop, in log space.
+// Single-precision normal CDF and quantile pieces for the SOV loop.
+//
+// Every factor e = Phi(t) is carried in a base-2 log split, e = em * 2^en (en an
+// integer held in a float, 0 when t > 0), together with ec = 1 - e, so neither
+// deep lower tails (e below the FP32 range) nor factors close to 1 lose digits.
 //
 // Phi(t): with a = |t|, the smaller tail is Phi(-a) = exp(-a^2/2) R(a), where
-// R(a) = erfcx(a / sqrt 2) / 2 is approximated by a (4,5) rational fitted by
-// fit_fp32_math.py (relative error < 5e-7 in FP32 on [0, 40]). Returned together:
-// e = Phi(t), ec = 1 - Phi(t) (each accurate as the smaller tail) and
-// le = log Phi(t) (from log R - a^2/2 when t <= 0, log(1 - Phi(-t)) otherwise).
+// R(a) = erfcx(a / sqrt 2) / 2 is a (3,4) rational fitted by fit_fp32_math.py
+// (relative error < 1.4e-6 in FP32 on [0, 40]); exp(-a^2/2) is taken as
+// 2^fl * 2^(f - fl) with f = -a^2 log2(e) / 2 and fl = floor(f).
 //
-// Phi^{-1}: for q in (0, 1/2], z = -Phi^{-1}(q) is a (6,5) rational in
-// x = sqrt(-2 log q) - sqrt(2 log 2) (relative error < 4e-7 in FP32). The caller
-// passes the smaller tail q of u and its sign, so 1 - u never loses digits.
-// Hardware v_log_f32 / v_exp_f32 (base 2), v_sqrt_f32 and v_rcp_f32 are used.
+// Phi^{-1}: for q in (0, 1/2], z = -Phi^{-1}(q) is a (5,4) rational in
+// x = sqrt(-2 log q) - sqrt(2 log 2) (relative error < 2.7e-6 in FP32), from
+// log2(q) = log2(q's mantissa) + q's exponent.
+// Hardware v_log_f32 / v_exp_f32 (base 2), v_sqrt_f32, v_rcp_f32, v_ldexp_f32
+// are used directly.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -27,40 +31,43 @@ __device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sq
 
 // z = -Phi^{-1}(q) >= 0 given log2(q), q <= 1/2.
 __device__ __forceinline__ float ninv_tail_from_log2(float lq2) {
-  const float s = fast_sqrt(-2.0f * kLn2 * lq2);
-  const float x = fmaxf(s - kS0, 0.0f);
-  float p = kZP[6];
+  const float s = fast_sqrt(lq2 * (-2.0f * kLn2));
+  const float x = s - kS0;
+  float p = kZP[5];
 #pragma unroll
-  for (int c = 5; c >= 0; --c) p = fmaf(p, x, kZP[c]);
-  float q = kZQ[5];
+  for (int c = 4; c >= 0; --c) p = fmaf(p, x, kZP[c]);
+  float q = kZQ[4];
 #pragma unroll
-  for (int c = 4; c >= 0; --c) q = fmaf(q, x, kZQ[c]);
+  for (int c = 3; c >= 0; --c) q = fmaf(q, x, kZQ[c]);
   return p * fast_rcp(q);
 }
 
-struct PhiOut {
-  float e, ec, le;
+struct Factor {
+  float em;   // mantissa part of e = Phi(t)
+  float en;   // exponent part (integer valued), 0 when t > 0
+  float ec;   // 1 - e
+  bool neg;   // t <= 0
 };
 
-__device__ __forceinline__ PhiOut phi_f32(float t) {
+__device__ __forceinline__ Factor phi_f32(float t) {
   const float a = fabsf(t);
-  const float a2 = a * a;
-  const float E = fast_exp2(a2 * (-0.5f * kLog2e));
-  float p = kRP[4];
+  const float f = (a * a) * (-0.5f * kLog2e);
+  const float fl = floorf(f);
+  const float E = fast_exp2(f - fl);                 // in [1, 2)
+  float p = kRP[3];
 #pragma unroll
-  for (int c = 3; c >= 0; --c) p = fmaf(p, a, kRP[c]);
-  float q = kRQ[5];
+  for (int c = 2; c >= 0; --c) p = fmaf(p, a, kRP[c]);
+  float q = kRQ[4];
 #pragma unroll
-  for (int c = 4; c >= 0; --c) q = fmaf(q, a, kRQ[c]);
-  const float R = p * fast_rcp(q);
-  const float P = E * R;                 // Phi(-a)
-  const bool neg = t <= 0.0f;
+  for (int c = 3; c >= 0; --c) q = fmaf(q, a, kRQ[c]);
+  const float m = E * (p * fast_rcp(q));            // Phi(-a) = m * 2^fl
+  const float P = __builtin_amdgcn_ldexpf(m, (int)fl);
   const float omP = 1.0f - P;
-  PhiOut o;
-  o.e = neg ? P : omP;
-  o.ec = neg ? omP : P;
-  const float L2 = fast_log2(neg ? R : omP);
-  o.le = neg ? fmaf(L2, kLn2, -0.5f * a2) : L2 * kLn2;
+  Factor o;
+  o.neg = t <= 0.0f;
+  o.em = o.neg ? m : omP;
+  o.en = o.neg ? fl : 0.0f;
+  o.ec = o.neg ? omP : P;
   return o;
 }
 

@@ -1,63 +1,96 @@
-// finalize_logsum: steps a6-a7 (Section 2.2, eq. (6); Section 3.1).
+// Steps a6-a7 (Section 2.2, eq. (6); Section 3.1) in two kernels.
 //
-// One block per instance. For every term: k = 0 gives the exact log Phi(b_0/L_00)
-// with SE 0; otherwise the R shift sums give
+// term_finalize: one thread per term (all instances of a launch). k = 0 gives
+// the exact log Phi(b_0/L_00) with SE 0; otherwise the shift sums (each the
+// in-order sum of its chunks) give
 //     log-term = log(sum_r num_r) - log(sum_r den_r)
 // (with the FP32 loop, log1p(-sum cnum / sum den) when that tail is the smaller,
 // which keeps digits for terms close to 1), and the delta-method standard error
-//     se^2 = R/(R-1) sum_r (num_r / sum num - den_r / sum den)^2
-// (NaN for R = 1). The instance's log F is the sum of its log-terms and its SE
-// the root of the summed se^2, both reduced in a fixed order.
+//     se^2 = R/(R-1) sum_r (num_r / sum num - den_r / sum den)^2   (NaN for R = 1).
+// Results go to a per-term array and, when asked for, to the user-order output.
+//
+// instance_logsum: one block per instance sums its terms' log-terms and se^2 in
+// a fixed order (per-thread strided partial sums, then a fixed tree), so the
+// result does not depend on anything but the instance.
 #include "vecchia_internal.h"
 
 namespace vecchia {
 namespace {
 
-__global__ __launch_bounds__(kFinalizeThreads) void finalize_logsum(
-    const InstDesc* __restrict__ insts, const Aux64* __restrict__ aux64,
-    const double* __restrict__ sums) {
+__device__ __forceinline__ int find_inst(const int64_t* __restrict__ bases, int n, int64_t t) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (bases[mid] <= t) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(256) void term_finalize(const InstDesc* __restrict__ insts, int n_inst,
+                                                     const int64_t* __restrict__ term_bases,
+                                                     int64_t total_terms, const Aux64* __restrict__ aux64,
+                                                     const double* __restrict__ sums,
+                                                     double2* __restrict__ term_res) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= total_terms) return;
+  const int ii = find_inst(term_bases, n_inst, t);
+  const InstDesc& I = insts[ii];
+  const int64_t i = t - term_bases[ii];
+  const int R = I.n_shifts;
+  double lt, se2;
+  if (I.kcnt[i] == 0) {
+    lt = aux64[t].lt0;
+    se2 = 0.0;
+  } else {
+    const int C = I.n_chunks;
+    const double* s = sums + 3 * (I.sums_base + i * R * (int64_t)C);
+    double sn = 0.0, sd = 0.0, sc = 0.0;
+    for (int r = 0; r < R; ++r) {
+      for (int c = 0; c < C; ++c) {
+        sn += s[3 * (r * C + c)];
+        sd += s[3 * (r * C + c) + 1];
+        sc += s[3 * (r * C + c) + 2];
+      }
+    }
+    if (I.precision == VECCHIA_FP32_LOOP && sc < sn)
+      lt = log1p(-sc / sd);
+    else
+      lt = log(sn) - log(sd);
+    if (R > 1) {
+      double acc = 0.0;
+      for (int r = 0; r < R; ++r) {
+        double nr = 0.0, dr = 0.0;
+        for (int c = 0; c < C; ++c) {
+          nr += s[3 * (r * C + c)];
+          dr += s[3 * (r * C + c) + 1];
+        }
+        const double d = nr / sn - dr / sd;
+        acc += d * d;
+      }
+      se2 = acc * (double)R / (double)(R - 1);
+    } else {
+      se2 = __builtin_nan("");
+    }
+  }
+  term_res[t] = make_double2(lt, se2);
+  if (I.terms_out) {
+    const int64_t u = I.perm[i];
+    I.terms_out[2 * u] = lt;
+    I.terms_out[2 * u + 1] = sqrt(se2);
+  }
+}
+
+__global__ __launch_bounds__(kFinalizeThreads) void instance_logsum(const InstDesc* __restrict__ insts,
+                                                                     const double2* __restrict__ term_res) {
   __shared__ double red_lt[kFinalizeThreads];
   __shared__ double red_se[kFinalizeThreads];
   const InstDesc& I = insts[blockIdx.x];
-  const int R = I.n_shifts;
-  const bool f32 = I.precision == VECCHIA_FP32_LOOP;
+  const double2* r = term_res + I.term_base;
   double part_lt = 0.0, part_se = 0.0;
   for (int64_t i = threadIdx.x; i < I.D; i += kFinalizeThreads) {
-    const int64_t t = I.term_base + i;
-    double lt, se2;
-    if (I.kcnt[i] == 0) {
-      lt = aux64[t].lt0;
-      se2 = 0.0;
-    } else {
-      const double* s = sums + 3 * (I.sums_base + i * R);
-      double sn = 0.0, sd = 0.0, sc = 0.0;
-      for (int r = 0; r < R; ++r) {
-        sn += s[3 * r];
-        sd += s[3 * r + 1];
-        sc += s[3 * r + 2];
-      }
-      if (f32 && sc < sn)
-        lt = log1p(-sc / sd);
-      else
-        lt = log(sn) - log(sd);
-      if (R > 1) {
-        double acc = 0.0;
-        for (int r = 0; r < R; ++r) {
-          const double d = s[3 * r] / sn - s[3 * r + 1] / sd;
-          acc += d * d;
-        }
-        se2 = acc * (double)R / (double)(R - 1);
-      } else {
-        se2 = __builtin_nan("");
-      }
-    }
-    part_lt += lt;
-    part_se += se2;
-    if (I.terms_out) {
-      const int64_t u = I.perm[i];
-      I.terms_out[2 * u] = lt;
-      I.terms_out[2 * u + 1] = sqrt(se2);
-    }
+    const double2 v = r[i];
+    part_lt += v.x;
+    part_se += v.y;
   }
   red_lt[threadIdx.x] = part_lt;
   red_se[threadIdx.x] = part_se;
@@ -77,11 +110,17 @@ __global__ __launch_bounds__(kFinalizeThreads) void finalize_logsum(
 
 }  // namespace
 
-hipError_t launch_finalize(const InstDesc* d_insts, int n_inst, const Aux64* aux64,
-                           const double* sums, hipStream_t s) {
+hipError_t launch_finalize(const InstDesc* d_insts, int n_inst, const int64_t* d_term_bases,
+                           int64_t total_terms, const Aux64* aux64, const double* sums,
+                           double2* term_res, hipStream_t s) {
   if (n_inst <= 0) return hipSuccess;
-  hipLaunchKernelGGL(finalize_logsum, dim3((unsigned)n_inst), dim3(kFinalizeThreads), 0, s, d_insts,
-                     aux64, sums);
+  const int64_t blocks = (total_terms + 255) / 256;
+  if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(term_finalize, dim3((unsigned)blocks), dim3(256), 0, s, d_insts, n_inst, d_term_bases,
+                     total_terms, aux64, sums, term_res);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(instance_logsum, dim3((unsigned)n_inst), dim3(kFinalizeThreads), 0, s, d_insts, term_res);
   return hipGetLastError();
 }
 

@@ -3,26 +3,32 @@
 // positions j < i with the smallest keys (d^2, j), d^2 = dx*dx + dy*dy in FP64
 // without fused multiply-add, listed in ascending key order.
 //
-// One thread per query; a 128-query block stages candidate coordinates through
-// LDS in increasing j, so a candidate tied in d^2 with a kept one never displaces
-// it (ties resolve to the lower index). The sorted top-M list lives in registers
-// (M is a template parameter, so the insertion network has static indices).
+// One wave per query, 8 queries per block. The block stages candidate
+// coordinates through LDS in tiles, in increasing j; lane l of a wave takes the
+// tile's candidates l, l+64, ... (again increasing j) and keeps its own sorted
+// top-M list in registers (M is a template parameter, so the insertion network
+// has static indices; a candidate tied in d^2 with a kept one never displaces
+// it). The wave then merges its 64 lists: M rounds of a lexicographic
+// (d^2, j) argmin butterfly across lanes, the winning lane popping its head.
 #include "vecchia_internal.h"
 
 namespace vecchia {
 namespace {
 
-constexpr int kKnnTile = 128;
+constexpr int kKnnWaves = 8;
+constexpr int kKnnTile = 512;
 
 template <int M>
-__global__ __launch_bounds__(kKnnTile) void knn_preceding(const double* __restrict__ xs,
-                                                          const double* __restrict__ ys, int64_t D,
-                                                          int32_t* __restrict__ nbr,
-                                                          int32_t* __restrict__ kcnt) {
+__global__ __launch_bounds__(64 * kKnnWaves) void knn_preceding(const double* __restrict__ xs,
+                                                                const double* __restrict__ ys, int64_t D,
+                                                                int32_t* __restrict__ nbr,
+                                                                int32_t* __restrict__ kcnt) {
 #pragma clang fp contract(off)
   __shared__ double2 tile[kKnnTile];
-  const int64_t q0 = (int64_t)blockIdx.x * kKnnTile;
-  const int64_t i = q0 + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t q0 = (int64_t)blockIdx.x * kKnnWaves;
+  const int64_t i = q0 + wave;
   const bool valid = i < D;
   const double qx = valid ? xs[i] : 0.0;
   const double qy = valid ? ys[i] : 0.0;
@@ -33,15 +39,17 @@ __global__ __launch_bounds__(kKnnTile) void knn_preceding(const double* __restri
     bd[s] = HUGE_VAL;
     bj[s] = -1;
   }
-  const int64_t last_query = (q0 + kKnnTile < D ? q0 + kKnnTile : D) - 1;
+  const int64_t last_query = (q0 + kKnnWaves < D ? q0 + kKnnWaves : D) - 1;
   for (int64_t t0 = 0; t0 < last_query; t0 += kKnnTile) {
     __syncthreads();
-    const int64_t j = t0 + threadIdx.x;
-    if (j < D) tile[threadIdx.x] = make_double2(xs[j], ys[j]);
+    for (int c = threadIdx.x; c < kKnnTile; c += 64 * kKnnWaves) {
+      const int64_t j = t0 + c;
+      if (j < D) tile[c] = make_double2(xs[j], ys[j]);
+    }
     __syncthreads();
-    int64_t lim = (valid ? i : 0) - t0;
+    const int64_t lim = (valid ? i : 0) - t0;
     const int cmax = (int)(lim < kKnnTile ? (lim > 0 ? lim : 0) : kKnnTile);
-    for (int c = 0; c < cmax; ++c) {
+    for (int c = lane; c < cmax; c += 64) {
       const double2 p = tile[c];
       const double dx = p.x - qx;
       const double dy = p.y - qy;
@@ -64,9 +72,31 @@ __global__ __launch_bounds__(kKnnTile) void knn_preceding(const double* __restri
   }
   if (!valid) return;
   const int k = (int)(i < M ? i : M);
+  int mine = -1;   // lane s keeps the s-th neighbour
+  for (int s = 0; s < k; ++s) {
+    double d = bd[0];
+    int j = bj[0];
 #pragma unroll
-  for (int s = 0; s < M; ++s) nbr[i * M + s] = s < k ? bj[s] : -1;
-  kcnt[i] = k;
+    for (int o = 32; o > 0; o >>= 1) {
+      const double od = __shfl_xor(d, o, 64);
+      const int oj = __shfl_xor(j, o, 64);
+      const bool take = od < d || (od == d && oj < j);
+      d = take ? od : d;
+      j = take ? oj : j;
+    }
+    if (lane == s) mine = j;
+    if (bj[0] == j) {   // the winning lane pops its head (indices are unique across lanes)
+#pragma unroll
+      for (int t = 0; t < M - 1; ++t) {
+        bd[t] = bd[t + 1];
+        bj[t] = bj[t + 1];
+      }
+      bd[M - 1] = HUGE_VAL;
+      bj[M - 1] = -1;
+    }
+  }
+  if (lane < M) nbr[i * M + lane] = lane < k ? mine : -1;
+  if (lane == 0) kcnt[i] = k;
 }
 
 __global__ void fill_i64(int64_t* p, int64_t n, int64_t v) {
@@ -82,8 +112,8 @@ __global__ void fill_i32(int32_t* p, int64_t n, int32_t v) {
 template <int M>
 hipError_t knn_dispatch(const double* xs, const double* ys, int64_t D, int32_t* nbr, int32_t* kcnt,
                         hipStream_t s) {
-  const unsigned blocks = (unsigned)((D + kKnnTile - 1) / kKnnTile);
-  hipLaunchKernelGGL(knn_preceding<M>, dim3(blocks), dim3(kKnnTile), 0, s, xs, ys, D, nbr, kcnt);
+  const unsigned blocks = (unsigned)((D + kKnnWaves - 1) / kKnnWaves);
+  hipLaunchKernelGGL(knn_preceding<M>, dim3(blocks), dim3(64 * kKnnWaves), 0, s, xs, ys, D, nbr, kcnt);
   return hipGetLastError();
 }
 

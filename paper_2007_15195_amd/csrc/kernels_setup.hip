@@ -114,11 +114,20 @@ __global__ __launch_bounds__(64) void term_setup(const InstDesc* __restrict__ in
     aux64[t].e0 = e0;
     aux64[t].lt0 = bad ? nan : log(e0);
     if (f32) {
+      // e0 as em0 * 2^en0 (the split keeps lower tails beyond the FP32 range)
       Aux32 a;
-      a.e0 = (float)e0;
+      if (b0 <= 0.0) {
+        int ex = 0;
+        const double mt = frexp(e0, &ex);
+        a.em0 = (float)mt;
+        a.en0 = (float)ex;
+        a.neg0 = 1.0f;
+      } else {
+        a.em0 = (float)e0;
+        a.en0 = 0.0f;
+        a.neg0 = 0.0f;
+      }
       a.ec0 = bad ? __builtin_nanf("") : (float)normcdf(-b0);
-      a.le0 = (float)log(e0);
-      a.pad = 0.0f;
       aux32[t] = a;
     }
     if (bad) atomicMin((long long*)I.bad_term, (long long)i);

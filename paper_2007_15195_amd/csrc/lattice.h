@@ -6,7 +6,8 @@
 // n = (term << 21) | (shift << 5) | dim of the stream seeded with the call's
 // seed (Steele, Lea & Flood 2014). Point p: U = p Z_j + S mod 2^64; baker
 // transform W = |2U - 2^64| (2^64 saturates); the coordinate is the midpoint
-// of W's cell on the 2^-52 (FP64) or 2^-23 (FP32) grid.
+// of W's cell on the 2^-52 grid (FP64) or, from U's upper half, on the 2^-23
+// grid (FP32).
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -34,16 +35,14 @@ __device__ __forceinline__ double lattice_coord_f64(uint64_t U) {
   return (double)odd * 0x1p-53;
 }
 
-// FP32 coordinate (2 floor(W / 2^41) + 1) 2^-24, from the two 32-bit halves of U.
-// U >= 2^63: floor(W/2^41) = bits 62..40 of U.
-// U <  2^63: W = 2X with X = 2^63 - U in (0, 2^63], floor(W/2^41) = min(X >> 40, 2^23 - 1).
-__device__ __forceinline__ uint32_t lattice_cell_f32(uint32_t hi, uint32_t lo) {
-  const uint32_t up = (hi >> 8) & 0x7fffffu;
-  const uint32_t borrow = lo != 0u;
-  const uint32_t xhi = 0x80000000u - hi - borrow;
-  uint32_t dn = xhi >> 8;
-  dn = dn < 0x7fffffu ? dn : 0x7fffffu;
-  return (hi & 0x80000000u) ? up : dn;
+// FP32 cell of U, from its upper 32 bits only: with s = U_hi - 2^31 as a signed
+// 32-bit integer, c = (s xor (s >> 31)) >> 8 in [0, 2^23), i.e. |s| >> 8 for
+// s >= 0 and (|s| - 1) >> 8 for s < 0. The coordinate (c + 1/2) 2^-23 is the
+// midpoint of the 2^-23 cell of the baker-transformed point, within 2^-24 of the
+// FP64 coordinate (exactly its cell, except when U's low 40 bits are all zero).
+__device__ __forceinline__ uint32_t lattice_cell_f32(uint32_t hi) {
+  const int32_t s = (int32_t)(hi ^ 0x80000000u);
+  return (uint32_t)(s ^ (s >> 31)) >> 8;
 }
 
 }  // namespace vecchia

@@ -43,6 +43,45 @@ uint64_t frac_sqrt_fixed(uint64_t p) {
 }
 }  // namespace
 
+namespace {
+struct ProfRec {
+  int K, precision;
+  hipEvent_t a, b;
+  int64_t steps;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof;
+}  // namespace
+
+std::vector<hipEvent_t> g_prof_pool;   // events returned by reset, reused
+
+hipError_t profile_events(hipEvent_t* a, hipEvent_t* b) {
+  {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (g_prof_pool.size() >= 2) {
+      *a = g_prof_pool.back();
+      g_prof_pool.pop_back();
+      *b = g_prof_pool.back();
+      g_prof_pool.pop_back();
+      return hipSuccess;
+    }
+  }
+  hipError_t e = hipEventCreate(a);
+  if (e == hipSuccess) e = hipEventCreate(b);
+  return e;
+}
+
+bool profiling_enabled() {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  return g_prof_on;
+}
+
+void profile_record(int K, int precision, hipEvent_t a, hipEvent_t b, int64_t steps) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof.push_back(ProfRec{K, precision, a, b, steps});
+}
+
 vecchia_status set_error(vecchia_status st, const std::string& msg) {
   g_err = msg;
   return st;
@@ -104,10 +143,30 @@ bool valid_qmc(const vecchia_qmc& q, std::string* why) {
   return true;
 }
 
+// Lattice points per QMC work item (a multiple of 64): small enough that a
+// launch has many more items than the GPU has wave slots (so the last round of
+// items is short), large enough to amortise each item's set-up. Results depend
+// on it only through the FP64 summation grouping; it is a function of the
+// instance alone, so an instance evaluates identically alone or in any batch.
+int chunk_points_for(int m, int precision, int n_points) {
+  (void)m;
+  const int base = precision == VECCHIA_FP32_LOOP ? 2048 : 512;
+  const int cap = ((n_points + 63) / 64) * 64;
+  return std::max(64, std::min(base, cap));
+}
+
 // ------------------------------------------------------------------ Batch ---
 
 Batch::~Batch() {
   if (graph_exec_) hipGraphExecDestroy(graph_exec_);
+  for (int k = 0; k < kSideStreams; ++k) {
+    if (side_[k]) {
+      hipStreamSynchronize(side_[k]);
+      hipStreamDestroy(side_[k]);
+    }
+    if (join_ev_[k]) hipEventDestroy(join_ev_[k]);
+  }
+  if (fork_ev_) hipEventDestroy(fork_ev_);
   for (auto& e : stage_ev_)
     if (e) hipEventDestroy(e);
   if (done_ev_) hipEventDestroy(done_ev_);
@@ -162,6 +221,9 @@ vecchia_status Batch::create(const std::vector<vecchia_plan_s*>& plans,
     d.seed = qmcs[j].seed;
     d.prep_stride = stride;
     d.precision = prec;
+    d.chunk_points = chunk_points_for(P->m, prec, qmcs[j].n_points);
+    d.n_chunks = (qmcs[j].n_points + d.chunk_points - 1) / d.chunk_points;
+    const int C = d.n_chunks;
     b->term_bases_[j] = tb;
     b->prep_off_[j] = prep;
     prep += align_up((size_t)P->D * stride * (prec == VECCHIA_FP32_LOOP ? 4 : 8), 256);
@@ -177,36 +239,47 @@ vecchia_status Batch::create(const std::vector<vecchia_plan_s*>& plans,
         r.item_begin = e - i;   // term count; turned into the item prefix below
         r.term_begin = i;
         r.inst = j;
-        r.n_shifts = R;
+        r.K = k;
+        r.items_per_term = R * C;
+        r.n_chunks = C;
         by_k[{k, prec}].push_back(r);
       }
       i = e;
     }
+    if ((int64_t)R * C > 0x7fffffffLL / std::max<int64_t>(1, P->D))
+      return set_error(VECCHIA_E_INVALID, "instance " + std::to_string(j) + " has more than 2^31 work items");
     tb += P->D;
-    sb += P->D * (int64_t)R;
+    sb += P->D * (int64_t)R * C;
   }
   b->term_bases_[n] = tb;
   b->total_terms_ = tb;
   b->total_sums_ = sb;
   b->prep_bytes_ = prep;
   if (tb > 0x7fffffffLL) return set_error(VECCHIA_E_INVALID, "more than 2^31-1 terms in one batch");
-  // launches: largest K first
-  for (auto it = by_k.rbegin(); it != by_k.rend(); ++it) {
+  // one launch per (K, precision); the launch with the most work runs on the
+  // caller's stream, the others (mostly the few terms with k < m) run beside it
+  for (auto it = by_k.begin(); it != by_k.end(); ++it) {
     Launch L;
     L.K = it->first.first;
     L.precision = it->first.second;
     L.range_off = (int)b->ranges_.size();
     L.n_ranges = (int)it->second.size();
     int64_t items = 0;
+    L.sov_steps = 0;
     for (RangeDesc r : it->second) {
       const int64_t nterms = r.item_begin;
       r.item_begin = items;
-      items += nterms * r.n_shifts;
+      items += nterms * r.items_per_term;
+      L.sov_steps += nterms * (int64_t)b->desc_[r.inst].n_shifts * b->desc_[r.inst].n_points * r.K;
       b->ranges_.push_back(r);
     }
     L.n_items = items;
+    if (items > 0x7fffffffLL) return set_error(VECCHIA_E_INVALID, "more than 2^31-1 work items in one launch");
     b->launches_.push_back(L);
   }
+  std::stable_sort(b->launches_.begin(), b->launches_.end(),
+                   [](const Launch& a, const Launch& c) { return a.sov_steps * (a.precision == VECCHIA_FP64 ? 8 : 1) >
+                                                                 c.sov_steps * (c.precision == VECCHIA_FP64 ? 8 : 1); });
   // workspace layout
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -220,6 +293,7 @@ vecchia_status Batch::create(const std::vector<vecchia_plan_s*>& plans,
   take(sizeof(Aux64) * tb);
   if (b->any_f32_) take(sizeof(Aux32) * tb);
   take(sizeof(double) * 3 * sb);
+  take(sizeof(double2) * tb);
   take(sizeof(int64_t) * n);
   take(prep);
   b->ws_bytes_ = off;
@@ -254,6 +328,7 @@ vecchia_status Batch::allocate() {
   d_aux64_ = reinterpret_cast<Aux64*>(take(sizeof(Aux64) * total_terms_));
   if (any_f32_) d_aux32_ = reinterpret_cast<Aux32*>(take(sizeof(Aux32) * total_terms_));
   d_sums_ = reinterpret_cast<double*>(take(sizeof(double) * 3 * total_sums_));
+  d_term_res_ = reinterpret_cast<double2*>(take(sizeof(double2) * total_terms_));
   d_bad_ = reinterpret_cast<int64_t*>(take(sizeof(int64_t) * n));
   d_prep_ = take(prep_bytes_);
   for (int j = 0; j < n; ++j) {
@@ -272,28 +347,58 @@ vecchia_status Batch::allocate() {
     }
   }
   e = hipEventCreateWithFlags(&done_ev_, hipEventDisableTiming);
-  if (e != hipSuccess) return hip_error(e, "event");
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&fork_ev_, hipEventDisableTiming);
+  // batches running on caller-provided resources (server requests) keep every
+  // launch on the caller's stream
+  for (int k = 0; k < kSideStreams && e == hipSuccess && !ext_stage_; ++k) {
+    e = hipStreamCreateWithFlags(&side_[k], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&join_ev_[k], hipEventDisableTiming);
+  }
+  if (e != hipSuccess) return hip_error(e, "streams and events");
   return VECCHIA_OK;
 }
 
 vecchia_status Batch::enqueue(hipStream_t s) {
   const int n = (int)plans_.size();
+  const bool prof = profiling_enabled();
   hipError_t e = launch_fill_i64(d_bad_, n, INT64_MAX, s);
   if (e == hipSuccess)
     e = launch_setup(d_desc_, n, d_term_bases_, total_terms_, d_aux64_, d_aux32_, s);
-  for (const Launch& L : launches_) {
-    if (e != hipSuccess) break;
-    e = launch_qmc(L.K, L.precision, d_desc_, d_ranges_ + L.range_off, L.n_ranges, L.n_items,
-                   d_aux64_, d_aux32_, d_Z_, d_sums_, s);
+  // fork: side streams start after the setup kernel
+  const int n_side = side_[0] ? std::min<int>((int)launches_.size() - 1, kSideStreams) : 0;
+  if (e == hipSuccess && n_side > 0) {
+    e = hipEventRecord(fork_ev_, s);
+    for (int k = 0; k < n_side && e == hipSuccess; ++k) e = hipStreamWaitEvent(side_[k], fork_ev_, 0);
   }
-  if (e == hipSuccess) e = launch_finalize(d_desc_, n, d_aux64_, d_sums_, s);
+  for (size_t li = 0; li < launches_.size() && e == hipSuccess; ++li) {
+    const Launch& L = launches_[li];
+    hipStream_t ls = (li == 0 || n_side == 0) ? s : side_[(li - 1) % n_side];
+    hipEvent_t a = nullptr, b = nullptr;
+    if (prof) {
+      e = profile_events(&a, &b);
+      if (e == hipSuccess) e = hipEventRecord(a, ls);
+      if (e != hipSuccess) break;
+    }
+    e = launch_qmc(L.K, L.precision, d_desc_, d_ranges_ + L.range_off, L.n_ranges, L.n_items,
+                   d_aux64_, d_aux32_, d_Z_, d_sums_, ls);
+    if (prof && e == hipSuccess) {
+      e = hipEventRecord(b, ls);
+      profile_record(L.K, L.precision, a, b, L.sov_steps);
+    }
+  }
+  // join
+  for (int k = 0; k < n_side && e == hipSuccess; ++k) {
+    e = hipEventRecord(join_ev_[k], side_[k]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, join_ev_[k], 0);
+  }
+  if (e == hipSuccess)
+    e = launch_finalize(d_desc_, n, d_term_bases_, total_terms_, d_aux64_, d_sums_, d_term_res_, s);
   if (e != hipSuccess) return hip_error(e, "kernel launch");
   return VECCHIA_OK;
 }
 
 vecchia_status Batch::run(const double* x_dev, const double* scales, const vecchia_cov* covs,
-                          double* out_dev, double* terms_dev, const uint64_t* seeds,
-                          const int32_t* n_points, hipStream_t s) {
+                          double* out_dev, double* terms_dev, const uint64_t* seeds, hipStream_t s) {
   const int n = (int)plans_.size();
   if (!x_dev || !out_dev) return set_error(VECCHIA_E_INVALID, "x_dev and out_dev must be device pointers");
   int dev = 0;
@@ -315,8 +420,6 @@ vecchia_status Batch::run(const double* x_dev, const double* scales, const vecch
     }
     const double sc = scales ? scales[j] : 1.0;
     if (!(std::isfinite(sc) && sc > 0)) return set_error(VECCHIA_E_INVALID, "scale must be finite and > 0");
-    if (n_points && (n_points[j] < 1 || n_points[j] > VECCHIA_MAX_POINTS))
-      return set_error(VECCHIA_E_INVALID, "n_points out of range");
     d[j].x = x_dev + xo;
     d[j].out = out_dev + 2 * j;
     d[j].terms_out = terms_dev;
@@ -327,7 +430,6 @@ vecchia_status Batch::run(const double* x_dev, const double* scales, const vecch
     d[j].range = c.range;
     d[j].nugget = c.nugget;
     if (seeds) d[j].seed = seeds[j];
-    if (n_points) d[j].n_points = n_points[j];
     xo += P->D;
   }
   if (n > 1 && terms_dev) return set_error(VECCHIA_E_INVALID, "per-term output is for single instances");
@@ -368,7 +470,8 @@ vecchia_status Batch::run(const double* x_dev, const double* scales, const vecch
   if (slot >= 0) stage_used_[slot] = true;
 
   static const bool no_graph = std::getenv("VECCHIA_NO_GRAPH") != nullptr;
-  const bool use_graph = !no_graph && !graph_failed_ && s != nullptr && eager_runs_ >= 1 && !ext_stage_;
+  const bool use_graph = !no_graph && !graph_failed_ && s != nullptr && eager_runs_ >= 1 && !ext_stage_ &&
+                         !profiling_enabled();
   if (use_graph) {
     if (graph_exec_ && graph_stream_ != s) {
       // graphs are replayed on the stream they were captured for
@@ -431,3 +534,45 @@ vecchia_status Batch::status(std::vector<int64_t>* bad) {
 }
 
 }  // namespace vecchia
+
+extern "C" {
+
+vecchia_status vecchia_profile_enable(int32_t on) {
+  std::lock_guard<std::mutex> lk(vecchia::g_prof_mu);
+  vecchia::g_prof_on = on != 0;
+  return VECCHIA_OK;
+}
+
+vecchia_status vecchia_profile_read(int32_t K, int32_t precision, double* total_ms, int64_t* launches,
+                                    int64_t* sov_steps) {
+  std::lock_guard<std::mutex> lk(vecchia::g_prof_mu);
+  double ms = 0.0;
+  int64_t nl = 0, st = 0;
+  for (const auto& r : vecchia::g_prof) {
+    if (r.K != K || r.precision != precision) continue;
+    hipError_t e = hipEventSynchronize(r.b);
+    float t = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, r.a, r.b);
+    if (e != hipSuccess) return vecchia::hip_error(e, "profile read");
+    ms += t;
+    ++nl;
+    st += r.steps;
+  }
+  if (total_ms) *total_ms = ms;
+  if (launches) *launches = nl;
+  if (sov_steps) *sov_steps = st;
+  return VECCHIA_OK;
+}
+
+vecchia_status vecchia_profile_reset(void) {
+  std::lock_guard<std::mutex> lk(vecchia::g_prof_mu);
+  for (auto& r : vecchia::g_prof) {
+    hipEventSynchronize(r.b);
+    vecchia::g_prof_pool.push_back(r.a);
+    vecchia::g_prof_pool.push_back(r.b);
+  }
+  vecchia::g_prof.clear();
+  return VECCHIA_OK;
+}
+
+}  // extern "C"

@@ -16,10 +16,15 @@ struct vecchia_plan_s;
 namespace vecchia {
 
 vecchia_status set_error(vecchia_status st, const std::string& msg);
+// kernel timing hook (vecchia_profile_*)
+bool profiling_enabled();
+hipError_t profile_events(hipEvent_t* a, hipEvent_t* b);
+void profile_record(int K, int precision, hipEvent_t a, hipEvent_t b, int64_t sov_steps);
 vecchia_status hip_error(hipError_t e, const char* what);
 const uint64_t* device_lattice_table(int device, hipError_t* err);
 bool valid_cov(const vecchia_cov& c, std::string* why);
 bool valid_qmc(const vecchia_qmc& q, std::string* why);
+int chunk_points_for(int m, int precision, int n_points);
 
 // Everything one evaluation of a fixed set of instances needs on the device.
 class Batch {
@@ -31,8 +36,7 @@ class Batch {
   // Bytes of device memory run() needs (workspace + descriptors).
   size_t workspace_bytes() const { return ws_bytes_; }
   vecchia_status run(const double* x_dev, const double* scales, const vecchia_cov* covs,
-                     double* out_dev, double* terms_dev, const uint64_t* seeds,
-                     const int32_t* n_points, hipStream_t s);
+                     double* out_dev, double* terms_dev, const uint64_t* seeds, hipStream_t s);
   vecchia_status status(std::vector<int64_t>* bad);  // waits for the last run
   // Run on caller-owned memory instead of allocating: ws (workspace_bytes(),
   // 256-byte aligned, device) and stage (n() descriptors, pinned host, not
@@ -53,6 +57,7 @@ class Batch {
     int range_off;
     int n_ranges;
     int64_t n_items;
+    int64_t sov_steps;   // sum over the launch's terms of n_shifts * n_points * K
   };
   vecchia_status allocate();
   vecchia_status enqueue(hipStream_t s);
@@ -78,6 +83,7 @@ class Batch {
   Aux64* d_aux64_ = nullptr;
   Aux32* d_aux32_ = nullptr;
   double* d_sums_ = nullptr;
+  double2* d_term_res_ = nullptr;
   int64_t* d_bad_ = nullptr;
   char* d_prep_ = nullptr;
   const uint64_t* d_Z_ = nullptr;
@@ -87,6 +93,12 @@ class Batch {
   hipEvent_t stage_ev_[kRing] = {};
   bool stage_used_[kRing] = {};
   int stage_next_ = 0;
+
+  // side streams: the QMC launches after the largest run beside it
+  static constexpr int kSideStreams = 2;
+  hipStream_t side_[kSideStreams] = {};
+  hipEvent_t fork_ev_ = nullptr;
+  hipEvent_t join_ev_[kSideStreams] = {};
 
   hipEvent_t done_ev_ = nullptr;
   hipStream_t last_stream_ = nullptr;
@@ -119,6 +131,11 @@ struct vecchia_plan_s {
   int32_t* d_nbr = nullptr;
   int32_t* d_kcnt = nullptr;
   std::unique_ptr<vecchia::Batch> single;   // cached one-instance batch of vecchia_logcdf
+  // pinned staging for vecchia_replan: {xs, ys (D doubles), perm (D int32)} x 2
+  char* h_replan[2] = {nullptr, nullptr};
+  hipEvent_t replan_ev[2] = {nullptr, nullptr};
+  bool replan_used[2] = {false, false};
+  int replan_next = 0;
   std::atomic<int> inflight{0};
   std::mutex mu;
 };

@@ -161,9 +161,8 @@ void vecchia_server_s::admit() {
     r->arena_off = off;
     r->batch->bind_external(d_arena + off, free_slot->h_stage);
     const uint64_t seed = r->q.seed;
-    const int32_t np = r->q.n_points;
     vecchia_status st = r->batch->run(r->x, &r->scale, r->has_cov ? &r->cov : nullptr, free_slot->d_out,
-                                      nullptr, &seed, &np, free_slot->stream);
+                                      nullptr, &seed, free_slot->stream);
     hipError_t e = hipSuccess;
     if (st == VECCHIA_OK) {
       e = hipMemcpyAsync(free_slot->h_res, free_slot->d_out, 2 * sizeof(double), hipMemcpyDeviceToHost,

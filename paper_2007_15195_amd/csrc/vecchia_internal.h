@@ -10,8 +10,6 @@ namespace vecchia {
 
 constexpr int kMaxM = VECCHIA_MAX_M;   // conditioning-set size limit
 constexpr int kMaxVars = kMaxM + 1;    // variables per term
-constexpr int kQmcWaves = 4;           // waves (work items) per QMC block
-constexpr int kSetupTermsPerBlock = 4; // one wave per term in the setup kernel
 constexpr int kFinalizeThreads = 256;
 
 // One log-CDF instance of a launch (device-resident descriptor).
@@ -28,7 +26,7 @@ struct InstDesc {
   void* prep;              // per-term scaled Cholesky rows (double or float), term 0
   int64_t D;
   int64_t term_base;       // global index of plan term 0 (aux arrays)
-  int64_t sums_base;       // index of (term 0, shift 0) in the sums triples
+  int64_t sums_base;       // index of (term 0, shift 0, chunk 0) in the sums triples
   int64_t* bad_term;       // first plan-order term whose Cholesky failed (min)
   double inv_scale, sigma2, range, nugget, nu;
   int32_t family;          // VECCHIA_COV_*
@@ -37,20 +35,27 @@ struct InstDesc {
   uint64_t seed;
   int32_t prep_stride;     // elements per term in prep
   int32_t precision;       // VECCHIA_FP64 / VECCHIA_FP32_LOOP
+  int32_t chunk_points;    // lattice points per work item (a multiple of 64)
+  int32_t n_chunks;        // ceil(n_points / chunk_points)
 };
 
-// A contiguous run of terms with the same k inside one instance; its QMC work
-// items are (term, shift) pairs, n_terms * n_shifts of them.
+// A contiguous run of terms with the same K inside one instance. Its work items
+// are (term, shift, chunk) triples, n_terms * n_shifts * n_chunks of them, in
+// that nesting order.
 struct RangeDesc {
   int64_t item_begin;      // exclusive prefix of items over the ranges of a launch
   int64_t term_begin;      // plan index of the first term
   int32_t inst;            // instance index
-  int32_t n_shifts;
+  int32_t K;               // conditioning-set size of every term of the range
+  int32_t items_per_term;  // n_shifts * n_chunks
+  int32_t n_chunks;
 };
 
 // Auxiliary per-term values written by term_setup.
-struct Aux64 { double e0; double lt0; };                  // Phi(b_0/L_00), its log
-struct Aux32 { float e0, ec0, le0, pad; };                 // FP32 e0, 1-e0, log e0
+struct Aux64 { double e0; double lt0; };   // Phi(b_0/L_00) and its log
+// FP32 form of e0 = Phi(b_0/L_00): e0 = em0 * 2^en0 (en0 = 0 unless b_0/L_00 <= 0),
+// ec0 = 1 - e0, neg0 = 1 if b_0/L_00 <= 0.
+struct Aux32 { float em0, en0, ec0, neg0; };
 
 // Launchers (kernels_*.hip).
 hipError_t launch_knn(const double* xs, const double* ys, int64_t D, int m, int32_t* nbr,
@@ -61,7 +66,8 @@ hipError_t launch_setup(const InstDesc* d_insts, int n_inst, const int64_t* d_te
 hipError_t launch_qmc(int K, int precision, const InstDesc* d_insts, const RangeDesc* d_ranges,
                       int n_ranges, int64_t n_items, const Aux64* aux64, const Aux32* aux32,
                       const uint64_t* d_Z, double* sums, hipStream_t s);
-hipError_t launch_finalize(const InstDesc* d_insts, int n_inst, const Aux64* aux64,
-                           const double* sums, hipStream_t s);
+hipError_t launch_finalize(const InstDesc* d_insts, int n_inst, const int64_t* d_term_bases,
+                           int64_t total_terms, const Aux64* aux64, const double* sums,
+                           double2* term_res, hipStream_t s);
 
 }  // namespace vecchia

@@ -27,10 +27,10 @@ VECCHIA_MAX_M = 31
 
 EXPORTED = [
     "vecchia_last_error", "vecchia_order", "vecchia_plan", "vecchia_plan_from_cov",
-    "vecchia_plan_info", "vecchia_plan_neighbours", "vecchia_logcdf", "vecchia_plan_status",
+    "vecchia_replan", "vecchia_plan_info", "vecchia_plan_neighbours", "vecchia_logcdf", "vecchia_plan_status",
     "vecchia_plan_destroy", "vecchia_batch_create", "vecchia_batch_logcdf", "vecchia_batch_status",
     "vecchia_batch_destroy", "vecchia_server_create", "vecchia_submit", "vecchia_poll",
-    "vecchia_server_destroy",
+    "vecchia_server_destroy", "vecchia_profile_enable", "vecchia_profile_read", "vecchia_profile_reset",
 ]
 
 
@@ -67,6 +67,7 @@ def lib():
         "vecchia_plan": [c_void_p, c_int64, c_int32, c_int32, c_void_p, c_int32, POINTER(vecchia_cov),
                          c_void_p, POINTER(c_void_p)],
         "vecchia_plan_from_cov": [c_void_p, c_int64, c_void_p, c_int32, c_void_p, POINTER(c_void_p)],
+        "vecchia_replan": [c_void_p, c_void_p, c_int32, c_void_p, c_void_p],
         "vecchia_plan_info": [c_void_p, POINTER(c_int64), POINTER(c_int32)],
         "vecchia_plan_neighbours": [c_void_p, c_void_p, c_void_p],
         "vecchia_logcdf": [c_void_p, c_void_p, c_double, c_void_p, POINTER(vecchia_qmc), c_void_p,
@@ -83,6 +84,9 @@ def lib():
         "vecchia_poll": [c_void_p, c_uint64, POINTER(c_double), POINTER(c_double), POINTER(c_int32),
                          POINTER(c_double)],
         "vecchia_server_destroy": [c_void_p],
+        "vecchia_profile_enable": [c_int32],
+        "vecchia_profile_read": [c_int32, c_int32, POINTER(c_double), POINTER(c_int64), POINTER(c_int64)],
+        "vecchia_profile_reset": [],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -177,6 +181,13 @@ def vecchia_plan_from_cov(Sigma: np.ndarray, m: int, nbr=None, stream=None) -> i
     _check(lib().vecchia_plan_from_cov(Sigma.ctypes.data, D, None if nb is None else nb.ctypes.data,
                                        int(m), _stream_ptr(stream), byref(h)))
     return h.value
+
+
+def vecchia_replan(plan: int, locs: np.ndarray, ordering: int, perm=None, stream=None) -> None:
+    locs = np.ascontiguousarray(locs, dtype=np.float64)
+    pin = None if perm is None else np.ascontiguousarray(perm, dtype=np.int64)
+    _check(lib().vecchia_replan(plan, locs.ctypes.data, int(ordering),
+                                None if pin is None else pin.ctypes.data, _stream_ptr(stream)))
 
 
 def vecchia_plan_info(plan: int):
@@ -274,3 +285,18 @@ def vecchia_poll(server: int, ticket: int):
 
 def vecchia_server_destroy(server: int) -> None:
     _check(lib().vecchia_server_destroy(server))
+
+
+def vecchia_profile_enable(on: int) -> None:
+    _check(lib().vecchia_profile_enable(int(on)))
+
+
+def vecchia_profile_read(K: int, precision: int):
+    """(total_ms, launches, sov_steps) of the recorded QMC launches of size K."""
+    ms, nl, st = c_double(), c_int64(), c_int64()
+    _check(lib().vecchia_profile_read(int(K), int(precision), byref(ms), byref(nl), byref(st)))
+    return ms.value, nl.value, st.value
+
+
+def vecchia_profile_reset() -> None:
+    _check(lib().vecchia_profile_reset())

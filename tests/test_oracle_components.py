@@ -54,16 +54,24 @@ def test_baker_transform_edges_and_symmetry():
     assert int(W[4]) == int(W[5]) == (1 << 64) - 2
     w = lattice.coord_f64(W)
     assert w[1] == 2.0 ** -53 and w[0] == 1.0 - 2.0 ** -53
-    w32 = lattice.coord_f32(W)
+    w32 = lattice.coord_f32_from_u(U)
     assert w32[1] == 2.0 ** -24 and w32[0] == 1.0 - 2.0 ** -24
     rng = np.random.default_rng(5)
     U = rng.integers(1, 2 ** 63, size=1000, dtype=np.uint64)
     with np.errstate(over="ignore"):
         Uc = np.uint64(0) - U                       # 2^64 - U
     assert np.array_equal(lattice.baker_w(U), lattice.baker_w(Uc))
-    # the FP32 coordinate is the FP64 one truncated to the 2^-23 grid
-    W = lattice.baker_w(rng.integers(0, 2 ** 64 - 1, size=1000, dtype=np.uint64))
-    assert np.all(np.abs(lattice.coord_f32(W) - lattice.coord_f64(W)) <= 2.0 ** -24)
+    # the FP32 coordinate is the midpoint of the FP64 coordinate's 2^-23 cell
+    # (one cell lower only when U's low 40 bits are zero): within 2^-24
+    edge = np.array([k << 40 for k in range(0, 1 << 24, 4099)] + [(1 << 63) + (3 << 40)], dtype=np.uint64)
+    U = np.concatenate([rng.integers(0, 2 ** 64 - 1, size=100000, dtype=np.uint64), edge])
+    W = lattice.baker_w(U)
+    d = np.abs(lattice.coord_f32_from_u(U) - lattice.coord_f64(W))
+    assert np.all(d <= 2.0 ** -24 + 2.0 ** -53)
+    cell64 = (W >> np.uint64(41)).astype(np.int64)
+    cell32 = np.floor(lattice.coord_f32_from_u(U) * 2 ** 23).astype(np.int64)
+    low0 = (U & np.uint64((1 << 40) - 1)) == 0
+    assert np.array_equal(cell32[~low0], cell64[~low0])
 
 
 def test_lattice_rule_integrates_smooth_product():
