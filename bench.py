@@ -32,16 +32,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # Dominant kernel figures used by the roofline (qmc_f32<10>, gfx950 build):
-# VALU instructions per SOV step counted in the kernel's unrolled chain from its
-# assembly (SQ_INSTS_VALU agrees: 60.8 per step including per-item overhead);
-# updated whenever the kernel changes.
-SLOTS_PER_STEP_F32_K10 = 60.1
+# VALU instructions per SOV step counted on the main path of the kernel's
+# unrolled chain in its assembly (536 per 10-step chain, rare branches not
+# taken); updated whenever the kernel changes.
+SLOTS_PER_STEP_F32_K10 = 53.6
 # MI355X FP32 vector peak 157.3 TFLOP/s = 256 CUs x 2.4 GHz x 128 FMA lanes x 2:
 # 78.64e12 full-rate VALU lane-slots per second.
 VALU_PEAK_TSLOTS = 256 * 2.4e9 * 128 / 1e12
 # HBM bytes per launch of qmc_f32<10> from rocprofv3 FETCH_SIZE x 2.0 +
 # WRITE_SIZE x 1.0 (factors from a 256 MiB copy); None once the kernel changes.
-TRAFFIC_BYTES_F32_K10 = 12.17e6
+TRAFFIC_BYTES_F32_K10 = 12.18e6
 
 
 def parse():
@@ -92,7 +92,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(the path shards by terms across GPUs, see DESIGN.md)", file=sys.stderr)
+              "(the terms of an instance are independent, so a multi-GPU run would split them by range)", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2007_15195_amd import vecchia as V
@@ -108,6 +108,7 @@ def main():
     out = torch.empty(2, dtype=torch.float64, device="cuda")
     q32 = V.make_qmc(inst.qmc.n_points, inst.qmc.n_shifts, inst.qmc.seed, V.VECCHIA_FP32_LOOP)
     q64 = V.make_qmc(inst.qmc.n_points, inst.qmc.n_shifts, inst.qmc.seed, V.VECCHIA_FP64)
+    torch.cuda.synchronize()                     # inputs resident before the bench stream uses them
     n_qmc_terms = D - 1 if m > 0 else 0          # terms with k >= 1 run the QMC loop
     samples_per_step = n_qmc_terms * inst.qmc.n_points * inst.qmc.n_shifts
 

@@ -24,9 +24,9 @@ Modules:
   sov         one Vecchia term: Cholesky + SOV chain + QMC mean and SE.
   vecchia     the whole log-CDF: order, neighbours, terms, log-space sum.
 
-Every reading of a point the paper leaves open is listed in the design doc of the
-repository (orderings, ties, lattice, shifts, SE, shared numerator/denominator
-points). Parity of the Vecchia approximation itself against the true CDF for
+Where the paper leaves a point open (orderings, ties, lattice, shifts, SE,
+shared numerator/denominator points), the module that takes the reading says
+which one it takes in its own header. Parity of the Vecchia approximation itself against the true CDF for
 m < D-1 and a general covariance is unpinned (no closed form exists); the tests
 pin every component and the exact special cases instead.
 """

@@ -152,62 +152,96 @@ __device__ __forceinline__ void item_f64(const Item& it, const Aux64* __restrict
   }
 }
 
+#ifndef VECCHIA_F32_CHAINS
+#define VECCHIA_F32_CHAINS 1
+#endif
+// Chains evaluated together per lane (independent lattice points interleaved
+// for instruction-level parallelism).
+constexpr int kF32Chains = VECCHIA_F32_CHAINS;
+
+// Global-address-space view of the rows (lets loads use a scalar base address).
+typedef __attribute__((address_space(1))) const float global_float;
+
 template <int K>
 __device__ __forceinline__ void item_f32(const Item& it, const Aux32* __restrict__ aux32,
                                          const uint64_t* __restrict__ Zg, double* __restrict__ sums) {
+  constexpr int H = kF32Chains;
   const InstDesc& I = *it.I;
   const int lane = threadIdx.x & 63;
-  const float* __restrict__ prep = reinterpret_cast<const float*>(I.prep) + it.i * I.prep_stride;
+  global_float* __restrict__ prep = (global_float*)(reinterpret_cast<const float*>(I.prep) + it.i * I.prep_stride);
   const Aux32 ax = aux32[it.t];
   const int p_begin = 1 + it.c * I.chunk_points;
   const int p_last = min(I.n_points, p_begin + I.chunk_points - 1);
-  Lattice<K> L;
-  L.init(I, it, (uint32_t)(p_begin + lane), Zg);
+  // chain h of a lane starts at point p_begin + 64 h + lane and strides 64 H
+  uint64_t U[H][K], st[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    const uint64_t S = lattice_shift(I.seed, it.i, it.r, j);
+    st[j] = Zg[j] * (uint64_t)(64 * H);
+#pragma unroll
+    for (int h = 0; h < H; ++h) U[h][j] = (uint64_t)(p_begin + 64 * h + lane) * Zg[j] + S;
+  }
   double acc_num = 0.0, acc_den = 0.0, acc_cnum = 0.0;
-  for (int p0 = p_begin; p0 <= p_last; p0 += 64) {
+  for (int p0 = p_begin; p0 <= p_last; p0 += 64 * H) {
     // compiler-only barrier: the term's rows are re-read (L1 hits) in every
     // iteration instead of being held in K(K+3)/2 registers across the loop
     __asm__ volatile("" ::: "memory");
-    const bool live = p0 + lane <= p_last;
-    float y[K];
-    Factor f;
-    f.em = ax.em0;
-    f.en = ax.en0;
-    f.ec = ax.ec0;
-    f.neg = ax.neg0 != 0.0f;
-    float qm = 1.0f, qe = 0.0f;   // product of e_1..e_{K-1} as qm * 2^qe
+    float y[H][K];
+    Factor f[H];
+    float qm[H], qe[H];   // product of e_1..e_{K-1} as qm * 2^qe
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+      f[h].em = ax.em0;
+      f[h].en = ax.en0;
+      f[h].m = ax.ec0;    // 1 - e_0 (used only when b'_0 > 0)
+      f[h].neg = ax.neg0 != 0.0f;
+      qm[h] = 1.0f;
+      qe[h] = 0.0f;
+    }
 #pragma unroll
     for (int a = 1; a <= K; ++a) {
-      const uint32_t cell = lattice_cell_f32(L.uh[a - 1]);
-      L.advance(a - 1);
-      const float w = fmaf((float)cell, 0x1p-23f, 0x1p-24f);
-      const float wc = 1.0f - w;
-      // y = Phi^{-1}(u), u = w e; u <= 1/2 whenever the previous t <= 0
-      const float um = w * f.em;
-      const bool lower = f.neg || um <= 0.5f;
-      const float qt = lower ? um : fmaf(w, f.ec, wc);
-      const float z = ninv_tail_from_log2(fast_log2(qt) + f.en);
-      y[a - 1] = lower ? -z : z;
-      const float* row = prep + a * (a + 1) / 2;
-      float acc = row[a];
+      global_float* row = prep + a * (a + 1) / 2;
 #pragma unroll
-      for (int c = 0; c < a; ++c) acc = fmaf(-row[c], y[c], acc);
-      f = phi_f32(acc);
-      if (a < K) {
-        qm *= f.em;
-        qe += f.en;
-        if (a % 8 == 0) {   // keep the mantissa product in range
-          qe += (float)__builtin_amdgcn_frexp_expf(qm);
-          qm = __builtin_amdgcn_frexp_mantf(qm);
+      for (int h = 0; h < H; ++h) {
+        const CoordF32 wp = lattice_coord_f32((uint32_t)(U[h][a - 1] >> 32));
+        const float w = wp.w;
+        U[h][a - 1] += st[a - 1];
+        // y = Phi^{-1}(u), u = w e; u <= 1/2 whenever the previous t <= 0, and
+        // otherwise 1 - u = (1 - w) + w (1 - e) keeps its digits
+        const float um = w * f[h].em;
+        const bool lower = f[h].neg || um <= 0.5f;
+        const float qt = lower ? um : fmaf(w, f[h].m, wp.wc);
+        const float z = ninv_tail_from_log2(fast_log2(qt) + f[h].en);
+        y[h][a - 1] = lower ? -z : z;
+        float acc = row[a];
+#pragma unroll
+        for (int c = 0; c < a; ++c) acc = fmaf(-row[c], y[h][c], acc);
+        f[h] = phi_f32(acc);
+        if (a < K) {
+          qm[h] *= f[h].em;
+          qe[h] += f[h].en;
+          // keep the mantissa product >= 2^-50 (factors are >= 2^-65): a
+          // wave-uniform branch taken only when some lane's product is that small
+          const bool low = qm[h] < 0x1p-50f;
+          if (__builtin_expect(__any(low), 0)) {
+            if (low) {
+              qe[h] += (float)__builtin_amdgcn_frexp_expf(qm[h]);
+              qm[h] = __builtin_amdgcn_frexp_mantf(qm[h]);
+            }
+          }
         }
       }
     }
-    if (live) {
-      const double den = ldexp((double)qm, (int)qe);
-      const double num = ldexp((double)(qm * f.em), (int)(qe + f.en));
-      acc_den += den;
-      acc_num += num;
-      acc_cnum = fma(den, (double)f.ec, acc_cnum);
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+      if (p0 + 64 * h + lane <= p_last) {
+        const double den = ldexp((double)qm[h], (int)qe[h]);
+        const double num = ldexp((double)(qm[h] * f[h].em), (int)(qe[h] + f[h].en));
+        const float ec = f[h].neg ? 1.0f - ldexpf(f[h].em, (int)f[h].en) : f[h].m;   // 1 - e_K
+        acc_den += den;
+        acc_num += num;
+        acc_cnum = fma(den, (double)ec, acc_cnum);
+      }
     }
   }
   acc_num = wave_sum(acc_num);
@@ -229,8 +263,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void qm
   item_f64<K>(it, aux64, Zg, sums);
 }
 
+// Minimum waves per SIMD requested for the FP32 chain of size K (caps the
+// registers of the unrolled chain; chosen so that no K spills).
+constexpr int f32_min_waves(int K) { return K <= 8 ? 8 : K <= 10 ? 6 : K <= 13 ? 5 : K <= 19 ? 4 : K <= 25 ? 3 : 2; }
+
 template <int K>
-__global__ __launch_bounds__(64) void qmc_f32(const InstDesc* __restrict__ insts,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(f32_min_waves(K)))) void qmc_f32(
+    const InstDesc* __restrict__ insts,
                                               const RangeDesc* __restrict__ ranges, int n_ranges,
                                               const Aux32* __restrict__ aux32,
                                               const uint64_t* __restrict__ Zg, double* __restrict__ sums) {

@@ -35,14 +35,22 @@ __device__ __forceinline__ double lattice_coord_f64(uint64_t U) {
   return (double)odd * 0x1p-53;
 }
 
-// FP32 cell of U, from its upper 32 bits only: with s = U_hi - 2^31 as a signed
-// 32-bit integer, c = (s xor (s >> 31)) >> 8 in [0, 2^23), i.e. |s| >> 8 for
-// s >= 0 and (|s| - 1) >> 8 for s < 0. The coordinate (c + 1/2) 2^-23 is the
-// midpoint of the 2^-23 cell of the baker-transformed point, within 2^-24 of the
-// FP64 coordinate (exactly its cell, except when U's low 40 bits are all zero).
-__device__ __forceinline__ uint32_t lattice_cell_f32(uint32_t hi) {
-  const int32_t s = (int32_t)(hi ^ 0x80000000u);
-  return (uint32_t)(s ^ (s >> 31)) >> 8;
+// FP32 coordinate of U, from its upper 32 bits only: with s = U_hi - 2^31 as a
+// signed 32-bit integer, the cell is c = |s| >> 8 for s >= 0 and
+// (|s| - 1) >> 8 for s < 0, and w = (c + 1/2) 2^-23, the midpoint of the 2^-23
+// cell of the baker-transformed point (within 2^-24 of the FP64 coordinate;
+// exactly its cell unless U's low 40 bits are all zero). With
+// g = (signed U_hi) >> 8 this is w = 1 - |g + 1/2| 2^-23, so 1 - w = |g + 1/2| 2^-23;
+// both are exact in FP32.
+struct CoordF32 {
+  float w, wc;   // w and 1 - w
+};
+__device__ __forceinline__ CoordF32 lattice_coord_f32(uint32_t hi) {
+  const float g = (float)((int32_t)hi >> 8);
+  CoordF32 c;
+  c.wc = fabsf(fmaf(g, 0x1p-23f, 0x1p-24f));
+  c.w = 1.0f - c.wc;
+  return c;
 }
 
 }  // namespace vecchia

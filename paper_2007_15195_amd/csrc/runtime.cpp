@@ -150,7 +150,12 @@ bool valid_qmc(const vecchia_qmc& q, std::string* why) {
 // instance alone, so an instance evaluates identically alone or in any batch.
 int chunk_points_for(int m, int precision, int n_points) {
   (void)m;
-  const int base = precision == VECCHIA_FP32_LOOP ? 2048 : 512;
+  // VECCHIA_CHUNK_F32 / VECCHIA_CHUNK_F64 override the default (measurement aid)
+  static const int env32 = std::getenv("VECCHIA_CHUNK_F32") ? std::atoi(std::getenv("VECCHIA_CHUNK_F32")) : 0;
+  static const int env64 = std::getenv("VECCHIA_CHUNK_F64") ? std::atoi(std::getenv("VECCHIA_CHUNK_F64")) : 0;
+  int base = precision == VECCHIA_FP32_LOOP ? 2048 : 512;
+  const int env = precision == VECCHIA_FP32_LOOP ? env32 : env64;
+  if (env >= 64) base = env / 64 * 64;
   const int cap = ((n_points + 63) / 64) * 64;
   return std::max(64, std::min(base, cap));
 }

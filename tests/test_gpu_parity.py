@@ -161,6 +161,18 @@ def test_fp32_tail_thresholds_relative_accuracy():
     assert d.max() < 1e-5
 
 
+def test_fp32_deep_conditional_limits():
+    # nugget 1e-8 and close neighbours: conditional limits reach t ~ -80, beyond
+    # the FP32 exponent range, and hundreds of steps fall in (-12.9, -11.9),
+    # where w * Phi(t) would be an FP32 denormal without the exponent split
+    inst = W.small_random_instance(500, 10, 51, n_points=2048, n_shifts=4, precision=W.PREC_FP32)
+    g = gpu_run(inst)
+    o = oracle_run(inst)
+    assert np.all(np.isfinite(g["terms"][:, 0]))
+    _compare_fp32(g, o)
+    assert abs(g["out"][0] - o["logF"]) <= FP32_REL_TOL * abs(o["logF"])
+
+
 # --------------------------------------------------------- closed forms ---
 
 def test_equicorrelated_orthant_through_gpu():

@@ -55,9 +55,11 @@ def test_graph_replays_match_eager_result():
     plan = V.vecchia_plan(inst.locs, inst.ordering, inst.m, inst.cov)
     stream = torch.cuda.Stream()
     x = torch.tensor(inst.x, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
     outs = []
     for rep in range(5):                       # call 1 eager, later calls replay a graph
         out = torch.full((2,), float("nan"), dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()               # the fill runs on torch's stream, not on `stream`
         V.vecchia_logcdf(plan, x, V.as_qmc(inst.qmc), out, stream=stream)
         torch.cuda.synchronize()
         outs.append(out.cpu().numpy())
@@ -68,6 +70,7 @@ def test_graph_replays_match_eager_result():
         assert np.array_equal(o, outs[0])
     # a different seed through the same graph changes the estimate
     out = torch.empty(2, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
     q = V.make_qmc(inst.qmc.n_points, inst.qmc.n_shifts, inst.qmc.seed + 1, inst.qmc.precision)
     V.vecchia_logcdf(plan, x, q, out, stream=stream)
     torch.cuda.synchronize()
