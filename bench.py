@@ -33,15 +33,15 @@ sys.path.insert(0, ROOT)
 
 # Dominant kernel figures used by the roofline (qmc_f32<10>, gfx950 build):
 # VALU instructions per SOV step counted on the main path of the kernel's
-# unrolled chain in its assembly (536 per 10-step chain, rare branches not
+# unrolled chain in its assembly (482 per 10-step chain, rare branches not
 # taken); updated whenever the kernel changes.
-SLOTS_PER_STEP_F32_K10 = 53.6
+SLOTS_PER_STEP_F32_K10 = 48.2
 # MI355X FP32 vector peak 157.3 TFLOP/s = 256 CUs x 2.4 GHz x 128 FMA lanes x 2:
 # 78.64e12 full-rate VALU lane-slots per second.
 VALU_PEAK_TSLOTS = 256 * 2.4e9 * 128 / 1e12
 # HBM bytes per launch of qmc_f32<10> from rocprofv3 FETCH_SIZE x 2.0 +
 # WRITE_SIZE x 1.0 (factors from a 256 MiB copy); None once the kernel changes.
-TRAFFIC_BYTES_F32_K10 = 12.18e6
+TRAFFIC_BYTES_F32_K10 = 12.20e6
 
 
 def parse():

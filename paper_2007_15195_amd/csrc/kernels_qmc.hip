@@ -42,6 +42,10 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// true when the predicate holds on some active lane (the ballot's mask is a
+// scalar, so the result is wave-uniform)
+__device__ __forceinline__ bool any_lane(bool p) { return __builtin_amdgcn_ballot_w64(p) != 0; }
+
 struct Item {
   const InstDesc* I;
   int64_t i;      // plan index of the term
@@ -152,97 +156,108 @@ __device__ __forceinline__ void item_f64(const Item& it, const Aux64* __restrict
   }
 }
 
-#ifndef VECCHIA_F32_CHAINS
-#define VECCHIA_F32_CHAINS 1
-#endif
-// Chains evaluated together per lane (independent lattice points interleaved
-// for instruction-level parallelism).
-constexpr int kF32Chains = VECCHIA_F32_CHAINS;
+constexpr float kDeepV = 7.74596669f;   // sqrt(60)
 
-// Global-address-space view of the rows (lets loads use a scalar base address).
+// Global-address-space view of the rows (vector loads with a scalar base
+// address; measured faster than scalar loads, which need an extra move per step
+// because a VALU instruction reads at most one SGPR).
 typedef __attribute__((address_space(1))) const float global_float;
 
+// FP32 chain of one lane. Factors are e = em * 2^en, with en = 0 except for
+// lower-tail factors below 2^-60 (t < -9.1), which keep 2^floor(-v^2) in en so
+// that em stays in [R, 2R). A wave-uniform flag `split` records that some
+// lane's current factor has en != 0; without it the step carries no exponent
+// arithmetic at all, and the wave takes the exponent branches only in the rare
+// steps that need them. The product of e_1..e_{K-1} is qm * 2^qe (qe an
+// integer), renormalised when some lane's qm falls below 2^-50; every factor
+// is >= 2^-65, so qm never leaves the normal range.
 template <int K>
 __device__ __forceinline__ void item_f32(const Item& it, const Aux32* __restrict__ aux32,
                                          const uint64_t* __restrict__ Zg, double* __restrict__ sums) {
-  constexpr int H = kF32Chains;
   const InstDesc& I = *it.I;
   const int lane = threadIdx.x & 63;
   global_float* __restrict__ prep = (global_float*)(reinterpret_cast<const float*>(I.prep) + it.i * I.prep_stride);
   const Aux32 ax = aux32[it.t];
+  const bool split0 = uniform(ax.en0 != 0.0f) != 0;
   const int p_begin = 1 + it.c * I.chunk_points;
   const int p_last = min(I.n_points, p_begin + I.chunk_points - 1);
-  // chain h of a lane starts at point p_begin + 64 h + lane and strides 64 H
-  uint64_t U[H][K], st[K];
+  // the lane's chain starts at point p_begin + lane and strides 64
+  uint64_t U[K], st[K];
 #pragma unroll
   for (int j = 0; j < K; ++j) {
     const uint64_t S = lattice_shift(I.seed, it.i, it.r, j);
-    st[j] = Zg[j] * (uint64_t)(64 * H);
-#pragma unroll
-    for (int h = 0; h < H; ++h) U[h][j] = (uint64_t)(p_begin + 64 * h + lane) * Zg[j] + S;
+    st[j] = Zg[j] * 64u;
+    U[j] = (uint64_t)(p_begin + lane) * Zg[j] + S;
   }
   double acc_num = 0.0, acc_den = 0.0, acc_cnum = 0.0;
-  for (int p0 = p_begin; p0 <= p_last; p0 += 64 * H) {
+  for (int p0 = p_begin; p0 <= p_last; p0 += 64) {
     // compiler-only barrier: the term's rows are re-read (L1 hits) in every
     // iteration instead of being held in K(K+3)/2 registers across the loop
     __asm__ volatile("" ::: "memory");
-    float y[H][K];
-    Factor f[H];
-    float qm[H], qe[H];   // product of e_1..e_{K-1} as qm * 2^qe
-#pragma unroll
-    for (int h = 0; h < H; ++h) {
-      f[h].em = ax.em0;
-      f[h].en = ax.en0;
-      f[h].m = ax.ec0;    // 1 - e_0 (used only when b'_0 > 0)
-      f[h].neg = ax.neg0 != 0.0f;
-      qm[h] = 1.0f;
-      qe[h] = 0.0f;
-    }
+    float y[K];
+    float em = ax.em0, en = ax.en0, m = ax.ec0;   // e_0 and 1 - e_0 (the latter used when t_0 > 0)
+    bool neg = ax.neg0 != 0.0f;
+    bool split = split0;
+    float qm = 1.0f;
+    int qe = 0;
 #pragma unroll
     for (int a = 1; a <= K; ++a) {
       global_float* row = prep + a * (a + 1) / 2;
+      const CoordF32 wp = lattice_coord_f32((uint32_t)(U[a - 1] >> 32));
+      U[a - 1] += st[a - 1];
+      // y = Phi^{-1}(u), u = w e; u <= 1/2 whenever the previous t <= 0, and
+      // otherwise 1 - u = (1 - w) + w (1 - e) keeps its digits
+      const float um = wp.w * em;
+      const bool lower = neg || um <= 0.5f;
+      const float qt = lower ? um : fmaf(wp.w, m, wp.wc);
+      const float lq = fast_log2(qt);
+      float z = ninv_tail_from_log2(lq);
+      if (__builtin_expect(split, 0)) {   // some lane's e carries 2^en
+        z = ninv_tail_from_log2(lq + en);
+        en = 0.0f;
+        split = false;
+      }
+      y[a - 1] = lower ? -z : z;
+      float v = row[a];
 #pragma unroll
-      for (int h = 0; h < H; ++h) {
-        const CoordF32 wp = lattice_coord_f32((uint32_t)(U[h][a - 1] >> 32));
-        const float w = wp.w;
-        U[h][a - 1] += st[a - 1];
-        // y = Phi^{-1}(u), u = w e; u <= 1/2 whenever the previous t <= 0, and
-        // otherwise 1 - u = (1 - w) + w (1 - e) keeps its digits
-        const float um = w * f[h].em;
-        const bool lower = f[h].neg || um <= 0.5f;
-        const float qt = lower ? um : fmaf(w, f[h].m, wp.wc);
-        const float z = ninv_tail_from_log2(fast_log2(qt) + f[h].en);
-        y[h][a - 1] = lower ? -z : z;
-        float acc = row[a];
-#pragma unroll
-        for (int c = 0; c < a; ++c) acc = fmaf(-row[c], y[h][c], acc);
-        f[h] = phi_f32(acc);
-        if (a < K) {
-          qm[h] *= f[h].em;
-          qe[h] += f[h].en;
-          // keep the mantissa product >= 2^-50 (factors are >= 2^-65): a
-          // wave-uniform branch taken only when some lane's product is that small
-          const bool low = qm[h] < 0x1p-50f;
-          if (__builtin_expect(__any(low), 0)) {
-            if (low) {
-              qe[h] += (float)__builtin_amdgcn_frexp_expf(qm[h]);
-              qm[h] = __builtin_amdgcn_frexp_mantf(qm[h]);
-            }
+      for (int c = 0; c < a; ++c) v = fmaf(-row[c], y[c], v);
+      const PhiParts ph = phi_f32(v);
+      em = ph.em;
+      m = ph.m;
+      neg = ph.neg;
+      // deep: Phi(t) < 2^-60, i.e. v < -sqrt(60); the compare's lane mask is
+      // taken directly (LLVM predicate 4 = ordered less-than)
+      if (__builtin_expect(__builtin_amdgcn_fcmpf(v, -kDeepV, 4) != 0, 0)) {
+        if (v < -kDeepV) {
+          // exponent kept outside the float (bounded so that qe cannot overflow)
+          const float fl = floorf(fmaxf(ph.f, -1048576.0f));
+          em = fast_exp2(fmaxf(ph.f, -1048576.0f) - fl) * ph.R;
+          en = fl;
+          if (a < K) qe += (int)fl;
+        }
+        split = true;
+      }
+      if (a < K) {
+        qm *= em;
+        const bool low = qm < 0x1p-50f;
+        if (__builtin_expect(any_lane(low), 0)) {
+          if (low) {
+            qe += __builtin_amdgcn_frexp_expf(qm);
+            qm = __builtin_amdgcn_frexp_mantf(qm);
           }
         }
       }
     }
-#pragma unroll
-    for (int h = 0; h < H; ++h) {
-      if (p0 + 64 * h + lane <= p_last) {
-        const double den = ldexp((double)qm[h], (int)qe[h]);
-        const double num = ldexp((double)(qm[h] * f[h].em), (int)(qe[h] + f[h].en));
-        const float ec = f[h].neg ? 1.0f - ldexpf(f[h].em, (int)f[h].en) : f[h].m;   // 1 - e_K
-        acc_den += den;
-        acc_num += num;
-        acc_cnum = fma(den, (double)ec, acc_cnum);
-      }
-    }
+    // den = prod_{a<K} e_a, num = den e_K, cnum = den (1 - e_K); lanes past the
+    // chunk's last point contribute zero
+    const float qml = p0 + lane <= p_last ? qm : 0.0f;
+    const int enk = (int)en;
+    const double den = ldexp((double)qml, qe);
+    const double num = ldexp(den * (double)em, enk);
+    const float ec = neg ? 1.0f - ldexpf(em, enk) : m;
+    acc_den += den;
+    acc_num += num;
+    acc_cnum = fma(den, (double)ec, acc_cnum);
   }
   acc_num = wave_sum(acc_num);
   acc_den = wave_sum(acc_den);

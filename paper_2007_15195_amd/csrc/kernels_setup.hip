@@ -10,6 +10,7 @@
 // It also stores Phi(b_0/L_00), the exact value of a term with k = 0.
 // A pivot <= 0 (or NaN) marks the term NOT_PD: its outputs become NaN and the
 // instance's bad_term is lowered to i.
+#include "fp32_math_coeffs.h"
 #include "vecchia_internal.h"
 
 namespace vecchia {
@@ -99,9 +100,11 @@ __global__ __launch_bounds__(64) void term_setup(const InstDesc* __restrict__ in
     const double laa = C[lane][lane];
     const int64_t off = i * (int64_t)I.prep_stride + (int64_t)lane * (lane + 1) / 2;
     if (f32) {
+      // the FP32 loop works with v = kappa t (exp(-t^2/2) = 2^(-v^2))
+      const double sc = kPhiScale / laa;
       float* row = reinterpret_cast<float*>(I.prep) + off;
-      for (int c = 0; c < lane; ++c) row[c] = (float)(C[lane][c] / laa);
-      row[lane] = bad ? __builtin_nanf("") : (float)(pb[lane] / laa);
+      for (int c = 0; c < lane; ++c) row[c] = (float)(C[lane][c] * sc);
+      row[lane] = bad ? __builtin_nanf("") : (float)(pb[lane] * sc);
     } else {
       double* row = reinterpret_cast<double*>(I.prep) + off;
       for (int c = 0; c < lane; ++c) row[c] = C[lane][c] / laa;
@@ -114,18 +117,18 @@ __global__ __launch_bounds__(64) void term_setup(const InstDesc* __restrict__ in
     aux64[t].e0 = e0;
     aux64[t].lt0 = bad ? nan : log(e0);
     if (f32) {
-      // e0 as em0 * 2^en0 (the split keeps lower tails beyond the FP32 range)
+      // e0 as em0 * 2^en0: split only below 2^-100 (the loop's first quantile
+      // argument w e0 then stays a normal FP32 number)
       Aux32 a;
-      if (b0 <= 0.0) {
+      a.neg0 = b0 <= 0.0 ? 1.0f : 0.0f;
+      if (e0 < 0x1p-100) {
         int ex = 0;
         const double mt = frexp(e0, &ex);
         a.em0 = (float)mt;
         a.en0 = (float)ex;
-        a.neg0 = 1.0f;
       } else {
         a.em0 = (float)e0;
         a.en0 = 0.0f;
-        a.neg0 = 0.0f;
       }
       a.ec0 = bad ? __builtin_nanf("") : (float)normcdf(-b0);
       aux32[t] = a;
