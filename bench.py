@@ -1,12 +1,13 @@
 """Benchmark of the Vecchia log-CDF hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--sections c2,c3,c4,c5]
 
-Workload (default): D = 2,500 locations uniform in [0,1]^2, Matern nu = 3/2
-(range 0.1, nugget 1e-8), maxmin ordering, m = 10, thresholds at the 0.9
-marginal quantile plus N(0, 0.1^2) noise, 10^4 lattice points x 10 shifts, FP32
-SOV loop with FP64 Cholesky / accumulation. Inputs are seeded synthetic data
-(workloads/); thresholds are resident on the device before timing.
+Headline workload (the JSON line's value): D = 2,500 locations uniform in
+[0,1]^2, Matern nu = 3/2 (range 0.1, nugget 1e-8), maxmin ordering, m = 10,
+thresholds at the 0.9 marginal quantile plus N(0, 0.1^2) noise, 10^4 lattice
+points x 10 shifts, FP32 SOV loop with FP64 Cholesky / accumulation. Inputs are
+seeded synthetic data (workloads/); thresholds are resident on the device
+before timing.
 
 One step = the whole path for one instance: vecchia_replan (host maxmin
 ordering + the GPU nearest-preceding-neighbour kernel) followed by
@@ -14,8 +15,17 @@ vecchia_logcdf (covariance + Cholesky, the QMC kernels, the segmented log-sum).
 K steps are timed between two device synchronisations; value = terms per second
 (D terms per step). The line also carries samples/s, the log-CDF-only rate,
 the plain FP64 rate on the same inputs, the FP32-vs-FP64 error, the roofline of
-the dominant kernel (its HIP-event time over the timed region) and the CPU
-oracle baseline on a bounded sample.
+the dominant kernel (its HIP-event time over the timed region), the CPU oracle
+baseline on a bounded sample, and one object per further workload:
+  c3_batched  512 instances (D log-uniform in [100, 20000], m in {5,10,15,20},
+              nu in {0.5,1.5,2.5}) in one batched evaluation, 4096 x 8 points;
+  c4_large    D = 250,000, m = 20, thresholds at the 0.95 quantile, FP32 and
+              FP64 on the same plan, 10^4 x 10 points;
+  c5_serving  mixed requests (D in [1000, 100000], m in 5..30, per-request
+              range and scale factor, 2048-8192 x 8 points) through the serving
+              loop: capacity with every request queued at once, then Poisson
+              arrivals at 80 % of it with p50/p99 latency.
+The launch shape of each workload is set by vecchia_autotune beforehand.
 """
 from __future__ import annotations
 
@@ -56,6 +66,10 @@ def parse():
     ap.add_argument("--cpu-terms", type=int, default=500)
     ap.add_argument("--fp32-only", action="store_true",
                     help="time the full FP32 step only (short runs under a profiler)")
+    ap.add_argument("--sections", default="c2,c3,c4,c5",
+                    help="comma list of workloads to run besides the headline (c2 is always run)")
+    ap.add_argument("--serving-requests", type=int, default=200)
+    ap.add_argument("--no-autotune", action="store_true")
     return ap.parse_args()
 
 
@@ -88,6 +102,158 @@ def cpu_baseline(inst, n_terms):
                       f"terms ({t_terms:.2f} s on {procs} processes), extrapolated to all terms"}
 
 
+def autotune(V, n_points, n_shifts, ms, sp):
+    """Launch shape for both precisions at this workload's N, R and m values."""
+    t0 = time.perf_counter()
+    c32, _ = V.vecchia_autotune(V.VECCHIA_FP32_LOOP, n_points, n_shifts, ms, stream=sp)
+    c64, _ = V.vecchia_autotune(V.VECCHIA_FP64, n_points, n_shifts, ms, stream=sp)
+    return {"n_points": n_points, "n_shifts": n_shifts, "m": list(ms), "chunk_points_fp32": c32,
+            "chunk_points_fp64": c64, "seconds": time.perf_counter() - t0}
+
+
+def _timed(torch, fn, reps):
+    fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps
+
+
+def bench_c3(V, torch, args):
+    """512 instances of mixed D, m and nu in one batched evaluation (FP32 loop)."""
+    import workloads as W
+    insts = W.batched_uneven()
+    stream = torch.cuda.Stream()
+    sp = stream.cuda_stream
+    tuned = None if args.no_autotune else autotune(V, 4096, 8, [5, 10, 15, 20], sp)
+    t0 = time.perf_counter()
+    plans = [V.vecchia_plan(i.locs, i.ordering, i.m, i.cov, stream=sp) for i in insts]
+    t_plans = time.perf_counter() - t0
+    terms = sum(i.D for i in insts)
+    chains = sum(i.D * i.qmc.n_points * i.qmc.n_shifts for i in insts)
+    steps = sum(i.qmc.n_points * i.qmc.n_shifts * (i.m * (i.D - i.m) + i.m * (i.m - 1) // 2) for i in insts)
+    x = torch.tensor(np.concatenate([i.x for i in insts]), dtype=torch.float64, device="cuda")
+    out = torch.empty((len(insts), 2), dtype=torch.float64, device="cuda")
+    res = {"workload": "batched_uneven_512", "instances": len(insts), "terms": terms,
+           "plan_seconds_all": t_plans}
+    for name, prec, reps in (("fp32", V.VECCHIA_FP32_LOOP, 3), ("fp64", V.VECCHIA_FP64, 1)):
+        batch = V.vecchia_batch_create(plans, [V.make_qmc(i.qmc.n_points, i.qmc.n_shifts, i.qmc.seed, prec)
+                                               for i in insts])
+        torch.cuda.synchronize()
+        sec = _timed(torch, lambda: V.vecchia_batch_logcdf(batch, x, out, stream=sp), reps)
+        res[name] = {"ms": 1e3 * sec, "terms_per_s": terms / sec, "samples_per_s": chains / sec,
+                     "sov_steps_per_s": steps / sec}
+        bad = V.vecchia_batch_status(batch, len(insts))
+        res[name]["not_pd_instances"] = int(np.sum(bad >= 0))
+        if name == "fp32":
+            o32 = out.cpu().numpy().copy()
+        else:
+            o64 = out.cpu().numpy().copy()
+        V.vecchia_batch_destroy(batch)
+    rel = np.abs(o32[:, 0] - o64[:, 0]) / np.abs(o64[:, 0])
+    res["fp32_vs_fp64_rel_total"] = {"max": float(rel.max()), "median": float(np.median(rel))}
+    res["fp32_speedup"] = res["fp64"]["ms"] / res["fp32"]["ms"]
+    if tuned is not None:
+        res["autotune"] = tuned
+    for p in plans:
+        V.vecchia_plan_destroy(p)
+    return res
+
+
+def bench_c4(V, torch, args):
+    """D = 250,000, m = 20, thresholds at the 0.95 quantile: FP32 and FP64."""
+    import workloads as W
+    inst = W.uniform250k_tail()
+    stream = torch.cuda.Stream()
+    sp = stream.cuda_stream
+    tuned = None if args.no_autotune else autotune(V, inst.qmc.n_points, inst.qmc.n_shifts, [inst.m], sp)
+    t0 = time.perf_counter()
+    plan = V.vecchia_plan(inst.locs, inst.ordering, inst.m, inst.cov, stream=sp)
+    t_plan = time.perf_counter() - t0
+    x = torch.tensor(inst.x, dtype=torch.float64, device="cuda")
+    out = torch.empty(2, dtype=torch.float64, device="cuda")
+    terms = torch.empty((inst.D, 2), dtype=torch.float64, device="cuda")
+    N, R, m, D = inst.qmc.n_points, inst.qmc.n_shifts, inst.m, inst.D
+    steps = N * R * (m * (D - m) + m * (m - 1) // 2)
+    res = {"workload": inst.name, "D": D, "m": m, "n_points": N, "n_shifts": R, "plan_seconds": t_plan}
+    got = {}
+    for name, prec, reps in (("fp32", V.VECCHIA_FP32_LOOP, 3), ("fp64", V.VECCHIA_FP64, 1)):
+        q = V.make_qmc(N, R, inst.qmc.seed, prec)
+        sec = _timed(torch, lambda: V.vecchia_logcdf(plan, x, q, out, stream=sp), reps)
+        V.vecchia_logcdf(plan, x, q, out, terms=terms, stream=sp)
+        torch.cuda.synchronize()
+        got[name] = (out.cpu().numpy().copy(), terms.cpu().numpy()[:, 0].copy())
+        res[name] = {"ms": 1e3 * sec, "terms_per_s": D / sec, "samples_per_s": D * N * R / sec,
+                     "sov_steps_per_s": steps / sec, "logF": float(got[name][0][0]), "se": float(got[name][0][1])}
+    res["fp32_speedup"] = res["fp64"]["ms"] / res["fp32"]["ms"]
+    d = np.abs(got["fp32"][1] - got["fp64"][1])
+    nz = got["fp64"][1] != 0.0          # log-terms that round to 0 in FP64 have no relative error
+    res["fp32_vs_fp64"] = {"rel_total": abs(got["fp32"][0][0] - got["fp64"][0][0]) / abs(got["fp64"][0][0]),
+                           "max_abs_term": float(d.max()),
+                           "max_rel_term": float(np.max(d[nz] / np.abs(got["fp64"][1][nz]))),
+                           "terms_rounding_to_zero": int(np.sum(~nz))}
+    if tuned is not None:
+        res["autotune"] = tuned
+    V.vecchia_plan_destroy(plan)
+    return res
+
+
+def _serve(V, srv, plans, reqs, xs, arrivals):
+    """Submit each request at its arrival time (seconds from start), poll until
+    all are done; returns (wall seconds, latencies)."""
+    pending = {}
+    lat = []
+    t0 = time.perf_counter()
+    k = 0
+    while k < len(reqs) or pending:
+        now = time.perf_counter() - t0
+        while k < len(reqs) and arrivals[k] <= now:
+            r = reqs[k]
+            pending[k] = V.vecchia_submit(srv, plans[r.plan_id], xs[k], r.qmc, scale=r.scale, cov_override=r.cov)
+            k += 1
+        for j in list(pending):
+            got = V.vecchia_poll(srv, pending[j])
+            if got is not None:
+                lat.append(got[2])
+                del pending[j]
+        time.sleep(0.0002)
+    return time.perf_counter() - t0, np.array(lat)
+
+
+def bench_c5(V, torch, args):
+    """Serving loop: capacity, then Poisson arrivals at 80 % of it."""
+    import workloads as W
+    st = W.serving_stream(n_requests=args.serving_requests)
+    t0 = time.perf_counter()
+    plans = [V.vecchia_plan(p.locs, p.ordering, p.m, p.cov) for p in st.plans]
+    t_plans = time.perf_counter() - t0
+    xs = [torch.tensor(r.x, dtype=torch.float64, device="cuda") for r in st.requests]
+    torch.cuda.synchronize()
+    reqs = st.requests
+    terms = sum(st.plans[r.plan_id].D for r in reqs)
+    srv = V.vecchia_server_create(8 << 30, 16)
+    # warm-up: a few requests (first launches, graph-free server path)
+    _serve(V, srv, plans, reqs[:8], xs[:8], np.zeros(8))
+    wall, lat_cap = _serve(V, srv, plans, reqs, xs, np.zeros(len(reqs)))
+    rate = len(reqs) / wall
+    arr = np.array([r.arrival_s for r in reqs])
+    arr = arr / arr[-1] * (len(reqs) / (0.8 * rate))          # same Poisson pattern at 80 % load
+    wall80, lat = _serve(V, srv, plans, reqs, xs, arr)
+    V.vecchia_server_destroy(srv)
+    for p in plans:
+        V.vecchia_plan_destroy(p)
+    return {"workload": "serving_stream", "plans": len(plans), "requests": len(reqs),
+            "plan_seconds_all": t_plans, "hbm_budget_bytes": 8 << 30, "slots": 16,
+            "capacity": {"requests_per_s": rate, "terms_per_s": terms / wall},
+            "poisson_80pct": {"offered_requests_per_s": 0.8 * rate, "requests_per_s": len(reqs) / wall80,
+                              "terms_per_s": terms / wall80,
+                              "latency_ms_p50": 1e3 * float(np.percentile(lat, 50)),
+                              "latency_ms_p99": 1e3 * float(np.percentile(lat, 99)),
+                              "latency_ms_max": 1e3 * float(lat.max())}}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -103,6 +269,9 @@ def main():
     D, m = inst.D, inst.m
     stream = torch.cuda.Stream()
     sp = stream.cuda_stream
+    tuned = None
+    if not args.no_autotune and not args.fp32_only:
+        tuned = autotune(V, inst.qmc.n_points, inst.qmc.n_shifts, [m], sp)
     plan = V.vecchia_plan(inst.locs, inst.ordering, m, inst.cov, stream=sp)
     x = torch.tensor(inst.x, dtype=torch.float64, device="cuda")
     out = torch.empty(2, dtype=torch.float64, device="cuda")
@@ -200,6 +369,15 @@ def main():
                      "avg_launch_ms": kernel_avg_ms, "sov_steps_per_launch": steps_per_launch,
                      "slots_per_step": SLOTS_PER_STEP_F32_K10},
     }
+    if tuned is not None:
+        res["autotune"] = tuned
+    sections = set(args.sections.split(","))
+    if "c3" in sections:
+        res["c3_batched"] = bench_c3(V, torch, args)
+    if "c4" in sections:
+        res["c4_large"] = bench_c4(V, torch, args)
+    if "c5" in sections:
+        res["c5_serving"] = bench_c5(V, torch, args)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(inst, args.cpu_terms)
     print(json.dumps(res), flush=True)

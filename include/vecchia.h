@@ -192,6 +192,29 @@ vecchia_status vecchia_profile_read(int32_t K, int32_t precision, double* total_
                                     int64_t* sov_steps);
 vecchia_status vecchia_profile_reset(void);
 
+/* Launch-shape autotuner (the batched launch of Section 2.2, eq. (6): terms of
+ * all instances that share K run in one launch, one wave per work item of
+ * chunk_points lattice points of one shift of one term). For each K = ms[k]
+ * (n_ms values, each in 1..VECCHIA_MAX_M) it builds a synthetic instance
+ * through vecchia_plan (uniform points, coordinate ordering, Matern 3/2,
+ * m = K, enough terms for two full rounds of waves), times that K's launch for
+ * chunk sizes {256, 512, ..., 8192} (capped at n_points rounded up to 64) with
+ * HIP events on hip_stream (median of three), and records the fastest for
+ * (precision, K); instances whose plan has m = K use it from then on.
+ * chunk_out / ms_out (may be NULL): n_ms entries, the chosen chunk and its
+ * median launch time. Synchronises hip_stream; do not evaluate concurrently on
+ * other threads. Results depend on the chunk size only through the FP64
+ * grouping of partial sums. Errors: INVALID (bad precision, QMC sizes or m
+ * list), NOMEM, HIP. */
+vecchia_status vecchia_autotune(int32_t precision, int32_t n_points, int32_t n_shifts, const int32_t* ms,
+                                int32_t n_ms, void* hip_stream, int32_t* chunk_out, float* ms_out);
+
+/* Read or set the chunk size used for (precision, m); 0 means the built-in
+ * default (2048 FP32, 512 FP64). A set value must be a multiple of 64 in
+ * [64, 2^24]. Host-only. Errors: INVALID. */
+vecchia_status vecchia_tuning_get(int32_t precision, int32_t m, int32_t* chunk_points);
+vecchia_status vecchia_tuning_set(int32_t precision, int32_t m, int32_t chunk_points);
+
 /* Serving: a request loop with continuous batching. Requests are admitted in
  * arrival order while their workspace fits in hbm_budget_bytes and one of
  * max_slots execution slots (each its own stream) is free; admitted requests

@@ -14,11 +14,12 @@ from __future__ import annotations
 import numpy as np
 
 
-def knn_preceding(s: np.ndarray, m: int) -> list:
-    """For plan-ordered locations s (D x 2), return nbrs[i] (plan indices)."""
+def knn_preceding(s: np.ndarray, m: int, queries=None) -> list:
+    """For plan-ordered locations s (D x 2), return nbrs[i] (plan indices) for
+    every i, or for the plan positions in `queries` (in that order)."""
     D = s.shape[0]
     out = []
-    for i in range(D):
+    for i in (range(D) if queries is None else [int(q) for q in queries]):
         k = min(m, i)
         if k == 0:
             out.append(np.zeros(0, dtype=np.int64))

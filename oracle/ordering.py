@@ -31,19 +31,21 @@ def coord_order(locs: np.ndarray) -> np.ndarray:
     return np.lexsort((np.arange(D), locs[:, 1], locs[:, 0])).astype(np.int64)
 
 
-def maxmin_order(locs: np.ndarray) -> np.ndarray:
-    """O(D^2) maxmin ordering, written as its definition."""
+def maxmin_order(locs: np.ndarray, n_first: int | None = None) -> np.ndarray:
+    """O(D^2) maxmin ordering, written as its definition. n_first: return only
+    the first n_first plan positions (the same picks, the loop stops early)."""
     D = locs.shape[0]
     if D == 0:
         return np.zeros(0, dtype=np.int64)
+    n_out = D if n_first is None else max(1, min(D, int(n_first)))
     cx = (locs[:, 0].min() + locs[:, 0].max()) / 2.0
     cy = (locs[:, 1].min() + locs[:, 1].max()) / 2.0
     first = int(np.argmin(d2_to(locs, cx, cy)))        # argmin: first (lowest) index on ties
-    perm = np.empty(D, dtype=np.int64)
+    perm = np.empty(n_out, dtype=np.int64)
     perm[0] = first
     mind2 = d2_to(locs, locs[first, 0], locs[first, 1])
     mind2[first] = -np.inf
-    for t in range(1, D):
+    for t in range(1, n_out):
         j = int(np.argmax(mind2))                      # argmax: lowest index on ties
         perm[t] = j
         mind2 = np.minimum(mind2, d2_to(locs, locs[j, 0], locs[j, 1]))

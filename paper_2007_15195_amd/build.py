@@ -30,6 +30,7 @@ SOURCES = [
     "server.cpp",
     "api.cpp",
     "host_order.cpp",
+    "autotune.cpp",
 ]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-function",

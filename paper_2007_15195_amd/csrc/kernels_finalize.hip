@@ -1,8 +1,9 @@
 // Steps a6-a7 (Section 2.2, eq. (6); Section 3.1) in two kernels.
 //
-// term_finalize: one thread per term (all instances of a launch). k = 0 gives
-// the exact log Phi(b_0/L_00) with SE 0; otherwise the shift sums (each the
-// in-order sum of its chunks) give
+// term_finalize: one wave per term (all instances of a launch). k = 0 gives
+// the exact log Phi(b_0/L_00) with SE 0; otherwise the wave's lanes take the
+// shifts (lane r sums shift r's chunks in order), fixed butterflies give the
+// totals, and
 //     log-term = log(sum_r num_r) - log(sum_r den_r)
 // (with the FP32 loop, log1p(-sum cnum / sum den) when that tail is the smaller,
 // which keeps digits for terms close to 1), and the delta-method standard error
@@ -26,13 +27,21 @@ __device__ __forceinline__ int find_inst(const int64_t* __restrict__ bases, int 
   return lo;
 }
 
-__global__ __launch_bounds__(256) void term_finalize(const InstDesc* __restrict__ insts, int n_inst,
-                                                     const int64_t* __restrict__ term_bases,
-                                                     int64_t total_terms, const Aux64* __restrict__ aux64,
-                                                     const double* __restrict__ sums,
-                                                     double2* __restrict__ term_res) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= total_terms) return;
+constexpr int kFinalizeWaves = 4;
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__global__ __launch_bounds__(64 * kFinalizeWaves) void term_finalize(
+    const InstDesc* __restrict__ insts, int n_inst, const int64_t* __restrict__ term_bases,
+    int64_t total_terms, const Aux64* __restrict__ aux64, const double* __restrict__ sums,
+    double2* __restrict__ term_res) {
+  const int64_t t = (int64_t)blockIdx.x * kFinalizeWaves + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (t >= total_terms) return;   // t is the same on every lane of a wave
   const int ii = find_inst(term_bases, n_inst, t);
   const InstDesc& I = insts[ii];
   const int64_t i = t - term_bases[ii];
@@ -44,21 +53,22 @@ __global__ __launch_bounds__(256) void term_finalize(const InstDesc* __restrict_
   } else {
     const int C = I.n_chunks;
     const double* s = sums + 3 * (I.sums_base + i * R * (int64_t)C);
-    double sn = 0.0, sd = 0.0, sc = 0.0;
-    for (int r = 0; r < R; ++r) {
+    double pn = 0.0, pd = 0.0, pc = 0.0;
+    for (int r = lane; r < R; r += 64) {
       for (int c = 0; c < C; ++c) {
-        sn += s[3 * (r * C + c)];
-        sd += s[3 * (r * C + c) + 1];
-        sc += s[3 * (r * C + c) + 2];
+        pn += s[3 * (r * C + c)];
+        pd += s[3 * (r * C + c) + 1];
+        pc += s[3 * (r * C + c) + 2];
       }
     }
+    const double sn = wave_sum(pn), sd = wave_sum(pd), sc = wave_sum(pc);
     if (I.precision == VECCHIA_FP32_LOOP && sc < sn)
       lt = log1p(-sc / sd);
     else
       lt = log(sn) - log(sd);
     if (R > 1) {
       double acc = 0.0;
-      for (int r = 0; r < R; ++r) {
+      for (int r = lane; r < R; r += 64) {
         double nr = 0.0, dr = 0.0;
         for (int c = 0; c < C; ++c) {
           nr += s[3 * (r * C + c)];
@@ -67,16 +77,18 @@ __global__ __launch_bounds__(256) void term_finalize(const InstDesc* __restrict_
         const double d = nr / sn - dr / sd;
         acc += d * d;
       }
-      se2 = acc * (double)R / (double)(R - 1);
+      se2 = wave_sum(acc) * (double)R / (double)(R - 1);
     } else {
       se2 = __builtin_nan("");
     }
   }
-  term_res[t] = make_double2(lt, se2);
-  if (I.terms_out) {
-    const int64_t u = I.perm[i];
-    I.terms_out[2 * u] = lt;
-    I.terms_out[2 * u + 1] = sqrt(se2);
+  if (lane == 0) {
+    term_res[t] = make_double2(lt, se2);
+    if (I.terms_out) {
+      const int64_t u = I.perm[i];
+      I.terms_out[2 * u] = lt;
+      I.terms_out[2 * u + 1] = sqrt(se2);
+    }
   }
 }
 
@@ -114,10 +126,10 @@ hipError_t launch_finalize(const InstDesc* d_insts, int n_inst, const int64_t* d
                            int64_t total_terms, const Aux64* aux64, const double* sums,
                            double2* term_res, hipStream_t s) {
   if (n_inst <= 0) return hipSuccess;
-  const int64_t blocks = (total_terms + 255) / 256;
+  const int64_t blocks = (total_terms + kFinalizeWaves - 1) / kFinalizeWaves;
   if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(term_finalize, dim3((unsigned)blocks), dim3(256), 0, s, d_insts, n_inst, d_term_bases,
-                     total_terms, aux64, sums, term_res);
+  hipLaunchKernelGGL(term_finalize, dim3((unsigned)blocks), dim3(64 * kFinalizeWaves), 0, s, d_insts, n_inst,
+                     d_term_bases, total_terms, aux64, sums, term_res);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(instance_logsum, dim3((unsigned)n_inst), dim3(kFinalizeThreads), 0, s, d_insts, term_res);

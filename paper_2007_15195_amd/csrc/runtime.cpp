@@ -148,14 +148,22 @@ bool valid_qmc(const vecchia_qmc& q, std::string* why) {
 // items is short), large enough to amortise each item's set-up. Results depend
 // on it only through the FP64 summation grouping; it is a function of the
 // instance alone, so an instance evaluates identically alone or in any batch.
+namespace {
+std::atomic<int> g_chunk[2][kMaxM + 1];   // [precision][m]; 0 = untuned
+}  // namespace
+
+int tuned_chunk(int precision, int m) {
+  if ((precision != VECCHIA_FP64 && precision != VECCHIA_FP32_LOOP) || m < 0 || m > kMaxM) return 0;
+  return g_chunk[precision][m].load(std::memory_order_relaxed);
+}
+
+void set_tuned_chunk(int precision, int m, int chunk_points) {
+  g_chunk[precision][m].store(chunk_points, std::memory_order_relaxed);
+}
+
 int chunk_points_for(int m, int precision, int n_points) {
-  (void)m;
-  // VECCHIA_CHUNK_F32 / VECCHIA_CHUNK_F64 override the default (measurement aid)
-  static const int env32 = std::getenv("VECCHIA_CHUNK_F32") ? std::atoi(std::getenv("VECCHIA_CHUNK_F32")) : 0;
-  static const int env64 = std::getenv("VECCHIA_CHUNK_F64") ? std::atoi(std::getenv("VECCHIA_CHUNK_F64")) : 0;
-  int base = precision == VECCHIA_FP32_LOOP ? 2048 : 512;
-  const int env = precision == VECCHIA_FP32_LOOP ? env32 : env64;
-  if (env >= 64) base = env / 64 * 64;
+  int base = tuned_chunk(precision, m);
+  if (base <= 0) base = precision == VECCHIA_FP32_LOOP ? 2048 : 512;
   const int cap = ((n_points + 63) / 64) * 64;
   return std::max(64, std::min(base, cap));
 }
@@ -536,6 +544,31 @@ vecchia_status Batch::status(std::vector<int64_t>* bad) {
     }
   }
   return st;
+}
+
+vecchia_status Batch::time_main_launch(hipStream_t s, int reps, float* median_ms) {
+  if (!ran_ || launches_.empty() || reps < 1) return set_error(VECCHIA_E_INVALID, "nothing to time");
+  const Launch& L = launches_[0];
+  std::vector<hipEvent_t> ev(2 * reps, nullptr);
+  hipError_t e = hipSuccess;
+  for (auto& x : ev)
+    if (e == hipSuccess) e = hipEventCreate(&x);
+  for (int r = 0; r < reps && e == hipSuccess; ++r) {
+    e = hipEventRecord(ev[2 * r], s);
+    if (e == hipSuccess)
+      e = launch_qmc(L.K, L.precision, d_desc_, d_ranges_ + L.range_off, L.n_ranges, L.n_items, d_aux64_,
+                     d_aux32_, d_Z_, d_sums_, s);
+    if (e == hipSuccess) e = hipEventRecord(ev[2 * r + 1], s);
+  }
+  std::vector<float> t(reps, 0.0f);
+  if (e == hipSuccess) e = hipEventSynchronize(ev[2 * reps - 1]);
+  for (int r = 0; r < reps && e == hipSuccess; ++r) e = hipEventElapsedTime(&t[r], ev[2 * r], ev[2 * r + 1]);
+  for (auto& x : ev)
+    if (x) hipEventDestroy(x);
+  if (e != hipSuccess) return hip_error(e, "timing");
+  std::sort(t.begin(), t.end());
+  *median_ms = t[reps / 2];
+  return VECCHIA_OK;
 }
 
 }  // namespace vecchia

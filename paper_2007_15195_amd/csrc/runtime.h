@@ -24,7 +24,12 @@ vecchia_status hip_error(hipError_t e, const char* what);
 const uint64_t* device_lattice_table(int device, hipError_t* err);
 bool valid_cov(const vecchia_cov& c, std::string* why);
 bool valid_qmc(const vecchia_qmc& q, std::string* why);
+// Lattice points per QMC work item for an instance with conditioning-set size
+// m: the autotuner's choice for (precision, m) when one was made, else the
+// default (2048 FP32 / 512 FP64), capped at N rounded up to 64.
 int chunk_points_for(int m, int precision, int n_points);
+int tuned_chunk(int precision, int m);            // 0 = not tuned
+void set_tuned_chunk(int precision, int m, int chunk_points);
 
 // Everything one evaluation of a fixed set of instances needs on the device.
 class Batch {
@@ -48,6 +53,9 @@ class Batch {
   const int64_t* device_bad_terms() const { return d_bad_; }
   int n() const { return (int)plans_.size(); }
   const std::vector<vecchia_qmc>& qmcs() const { return qmcs_; }
+  // After a completed run(): re-launches the launch with the most work `reps`
+  // times on s between HIP events and returns the median duration (autotuner).
+  vecchia_status time_main_launch(hipStream_t s, int reps, float* median_ms);
   hipStream_t last_stream() const { return last_stream_; }
 
  private:

@@ -31,6 +31,7 @@ EXPORTED = [
     "vecchia_plan_destroy", "vecchia_batch_create", "vecchia_batch_logcdf", "vecchia_batch_status",
     "vecchia_batch_destroy", "vecchia_server_create", "vecchia_submit", "vecchia_poll",
     "vecchia_server_destroy", "vecchia_profile_enable", "vecchia_profile_read", "vecchia_profile_reset",
+    "vecchia_autotune", "vecchia_tuning_get", "vecchia_tuning_set",
 ]
 
 
@@ -87,6 +88,9 @@ def lib():
         "vecchia_profile_enable": [c_int32],
         "vecchia_profile_read": [c_int32, c_int32, POINTER(c_double), POINTER(c_int64), POINTER(c_int64)],
         "vecchia_profile_reset": [],
+        "vecchia_autotune": [c_int32, c_int32, c_int32, c_void_p, c_int32, c_void_p, c_void_p, c_void_p],
+        "vecchia_tuning_get": [c_int32, c_int32, POINTER(c_int32)],
+        "vecchia_tuning_set": [c_int32, c_int32, c_int32],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -300,3 +304,25 @@ def vecchia_profile_read(K: int, precision: int):
 
 def vecchia_profile_reset() -> None:
     _check(lib().vecchia_profile_reset())
+
+
+def vecchia_autotune(precision: int, n_points: int, n_shifts: int, ms, stream=None):
+    """Tune the chunk size for each K in ms; returns (chunks, median_ms) lists."""
+    ms = [int(v) for v in ms]
+    arr = (c_int32 * max(1, len(ms)))(*ms)
+    chunks = (c_int32 * max(1, len(ms)))()
+    t = (ctypes.c_float * max(1, len(ms)))()
+    _check(lib().vecchia_autotune(int(precision), int(n_points), int(n_shifts), ctypes.cast(arr, c_void_p),
+                                  len(ms), _stream_ptr(stream), ctypes.cast(chunks, c_void_p),
+                                  ctypes.cast(t, c_void_p)))
+    return list(chunks)[:len(ms)], list(t)[:len(ms)]
+
+
+def vecchia_tuning_get(precision: int, m: int) -> int:
+    v = c_int32()
+    _check(lib().vecchia_tuning_get(int(precision), int(m), byref(v)))
+    return v.value
+
+
+def vecchia_tuning_set(precision: int, m: int, chunk_points: int) -> None:
+    _check(lib().vecchia_tuning_set(int(precision), int(m), int(chunk_points)))

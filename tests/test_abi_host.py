@@ -92,3 +92,25 @@ def test_plan_rejects_bad_arguments_before_gpu_work():
         V.vecchia_server_create(0, 4)
     assert e.value.status == 1
     assert "budget" in V.vecchia_last_error()
+
+
+def test_tuning_table_and_autotune_validation():
+    # the tuning table is host state: default 0, settable per (precision, m)
+    assert V.vecchia_tuning_get(V.VECCHIA_FP32_LOOP, 10) == 0
+    V.vecchia_tuning_set(V.VECCHIA_FP32_LOOP, 10, 1024)
+    try:
+        assert V.vecchia_tuning_get(V.VECCHIA_FP32_LOOP, 10) == 1024
+        assert V.vecchia_tuning_get(V.VECCHIA_FP64, 10) == 0
+    finally:
+        V.vecchia_tuning_set(V.VECCHIA_FP32_LOOP, 10, 0)
+    assert V.vecchia_tuning_get(V.VECCHIA_FP32_LOOP, 10) == 0
+    for bad in ((2, 10, 1024), (1, 32, 1024), (1, -1, 1024), (1, 10, 100), (1, 10, 32), (1, 10, 1 << 25)):
+        with pytest.raises(V.VecchiaError) as e:
+            V.vecchia_tuning_set(*bad)
+        assert e.value.status == 1
+    # the autotuner rejects bad arguments before any device work
+    for bad in ((2, 1000, 4, [3]), (1, 0, 4, [3]), (1, 1000, 0, [3]), (1, 1000, 4, []), (1, 1000, 4, [0]),
+                (1, 1000, 4, [5, 32])):
+        with pytest.raises(V.VecchiaError) as e:
+            V.vecchia_autotune(*bad, stream=0)
+        assert e.value.status == 1
