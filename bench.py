@@ -1,6 +1,6 @@
 """Benchmark of the Vecchia log-CDF hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--sections c2,c3,c4,c5]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--sections c1,c2,c3,c4,c5]
 
 Headline workload (the JSON line's value): D = 2,500 locations uniform in
 [0,1]^2, Matern nu = 3/2 (range 0.1, nugget 1e-8), maxmin ordering, m = 10,
@@ -17,6 +17,8 @@ K steps are timed between two device synchronisations; value = terms per second
 the plain FP64 rate on the same inputs, the FP32-vs-FP64 error, the roofline of
 the dominant kernel (its HIP-event time over the timed region), the CPU oracle
 baseline on a bounded sample, and one object per further workload:
+  c1_grid     D = 400 on a 20 x 20 grid, exponential covariance, coordinate
+              order, m = 5, 1000 x 10 points: the plain FP64 form (and FP32);
   c3_batched  512 instances (D log-uniform in [100, 20000], m in {5,10,15,20},
               nu in {0.5,1.5,2.5}) in one batched evaluation, 4096 x 8 points;
   c4_large    D = 250,000, m = 20, thresholds at the 0.95 quantile, FP32 and
@@ -66,7 +68,7 @@ def parse():
     ap.add_argument("--cpu-terms", type=int, default=500)
     ap.add_argument("--fp32-only", action="store_true",
                     help="time the full FP32 step only (short runs under a profiler)")
-    ap.add_argument("--sections", default="c2,c3,c4,c5",
+    ap.add_argument("--sections", default="c1,c2,c3,c4,c5",
                     help="comma list of workloads to run besides the headline (c2 is always run)")
     ap.add_argument("--serving-requests", type=int, default=200)
     ap.add_argument("--no-autotune", action="store_true")
@@ -119,6 +121,27 @@ def _timed(torch, fn, reps):
         fn()
     torch.cuda.synchronize()
     return (time.perf_counter() - t0) / reps
+
+
+def bench_c1(V, torch, args):
+    """400-point grid, exponential covariance, coordinate order, m = 5: the plain FP64 form."""
+    import workloads as W
+    inst = W.grid400_exponential()
+    stream = torch.cuda.Stream()
+    sp = stream.cuda_stream
+    plan = V.vecchia_plan(inst.locs, inst.ordering, inst.m, inst.cov, stream=sp)
+    x = torch.tensor(inst.x, dtype=torch.float64, device="cuda")
+    out = torch.empty(2, dtype=torch.float64, device="cuda")
+    N, R, m, D = inst.qmc.n_points, inst.qmc.n_shifts, inst.m, inst.D
+    res = {"workload": inst.name, "D": D, "m": m, "n_points": N, "n_shifts": R}
+    for name, prec in (("fp64", V.VECCHIA_FP64), ("fp32", V.VECCHIA_FP32_LOOP)):
+        q = V.make_qmc(N, R, inst.qmc.seed, prec)
+        sec = _timed(torch, lambda: V.vecchia_logcdf(plan, x, q, out, stream=sp), 20)
+        o = out.cpu().numpy()
+        res[name] = {"ms": 1e3 * sec, "terms_per_s": D / sec, "samples_per_s": D * N * R / sec,
+                     "logF": float(o[0]), "se": float(o[1])}
+    V.vecchia_plan_destroy(plan)
+    return res
 
 
 def bench_c3(V, torch, args):
@@ -372,6 +395,8 @@ def main():
     if tuned is not None:
         res["autotune"] = tuned
     sections = set(args.sections.split(","))
+    if "c1" in sections:
+        res["c1_grid"] = bench_c1(V, torch, args)
     if "c3" in sections:
         res["c3_batched"] = bench_c3(V, torch, args)
     if "c4" in sections:
