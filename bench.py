@@ -53,7 +53,7 @@ SLOTS_PER_STEP_F32_K10 = 48.2
 VALU_PEAK_TSLOTS = 256 * 2.4e9 * 128 / 1e12
 # HBM bytes per launch of qmc_f32<10> from rocprofv3 FETCH_SIZE x 2.0 +
 # WRITE_SIZE x 1.0 (factors from a 256 MiB copy); None once the kernel changes.
-TRAFFIC_BYTES_F32_K10 = 12.20e6
+TRAFFIC_BYTES_F32_K10 = 12.19e6
 
 
 def parse():

@@ -74,32 +74,11 @@ __device__ __forceinline__ Item decode_item(const InstDesc* __restrict__ insts,
   return it;
 }
 
-// Lattice state of one lane for K dimensions: U_j = p Z_j + S_j (mod 2^64) for
-// the lane's current point p; step_j = 64 Z_j.
-template <int K>
-struct Lattice {
-  uint32_t uh[K], ul[K], sh[K], sl[K];
-  __device__ __forceinline__ void init(const InstDesc& I, const Item& it, uint32_t p,
-                                       const uint64_t* __restrict__ Zg) {
-#pragma unroll
-    for (int j = 0; j < K; ++j) {
-      const uint64_t S = lattice_shift(I.seed, it.i, it.r, j);
-      const uint64_t u = (uint64_t)p * Zg[j] + S;
-      const uint64_t st = Zg[j] << 6;
-      uh[j] = (uint32_t)(u >> 32);
-      ul[j] = (uint32_t)u;
-      sh[j] = (uint32_t)(st >> 32);
-      sl[j] = (uint32_t)st;
-    }
-  }
-  __device__ __forceinline__ uint64_t u64(int j) const { return (uint64_t)uh[j] << 32 | ul[j]; }
-  __device__ __forceinline__ void advance(int j) {
-    const uint64_t u = u64(j) + ((uint64_t)sh[j] << 32 | sl[j]);
-    uh[j] = (uint32_t)(u >> 32);
-    ul[j] = (uint32_t)u;
-  }
-};
-
+// The term's scaled rows are staged in LDS once per work item (one wave per
+// block) and read from there in every step: broadcast reads at LDS latency
+// instead of L1/L2 round trips. Measured on gfx950 this is neutral for small K
+// and up to 1.3x (FP32) / 2.4x (FP64) faster for large K, whose rows no longer
+// fit the vector L1 beside the other resident waves.
 __device__ __forceinline__ double* item_out(const InstDesc& I, const Item& it, double* sums) {
   return sums + 3 * (I.sums_base + (it.i * I.n_shifts + it.r) * (int64_t)I.n_chunks + it.c);
 }
@@ -118,8 +97,15 @@ __device__ __forceinline__ void item_f64(const Item& it, const Aux64* __restrict
   const double e0 = aux64[it.t].e0;
   const int p_begin = 1 + it.c * I.chunk_points;
   const int p_last = min(I.n_points, p_begin + I.chunk_points - 1);
-  Lattice<K> L;
-  L.init(I, it, (uint32_t)(p_begin + lane), Zg);
+  // the lane's chain starts at point p_begin + lane and strides 64 (U_j += 64 Z_j)
+  uint64_t U[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j)
+    U[j] = (uint64_t)(p_begin + lane) * Zg[j] + lattice_shift(I.seed, it.i, it.r, j);
+  constexpr int kRowElems = (K + 1) * (K + 2) / 2;   // rows 0..K of the term's block
+  __shared__ double srow[kRowElems];
+  for (int e = lane; e < kRowElems; e += 64) srow[e] = prep[e];
+  __syncthreads();
   double acc_num = 0.0, acc_den = 0.0;
   for (int p0 = p_begin; p0 <= p_last; p0 += 64) {
     __asm__ volatile("" ::: "memory");   // re-read the term's rows each iteration
@@ -129,11 +115,11 @@ __device__ __forceinline__ void item_f64(const Item& it, const Aux64* __restrict
     bool alive = e0 > 0.0;
 #pragma unroll
     for (int a = 1; a <= K; ++a) {
-      const double w = lattice_coord_f64(L.u64(a - 1));
-      L.advance(a - 1);
+      const double w = lattice_coord_f64(U[a - 1]);
+      U[a - 1] += Zg[a - 1] << 6;
       const double u = fmax(w * e, 2.2250738585072014e-308);
       y[a - 1] = alive ? ncdfinv64(u) : 0.0;
-      const double* row = prep + a * (a + 1) / 2;
+      const double* row = srow + a * (a + 1) / 2;
       double acc = row[a];
 #pragma unroll
       for (int c = 0; c < a; ++c) acc -= row[c] * y[c];
@@ -158,10 +144,6 @@ __device__ __forceinline__ void item_f64(const Item& it, const Aux64* __restrict
 
 constexpr float kDeepV = 7.74596669f;   // sqrt(60)
 
-// Global-address-space view of the rows (vector loads with a scalar base
-// address; measured faster than scalar loads, which need an extra move per step
-// because a VALU instruction reads at most one SGPR).
-typedef __attribute__((address_space(1))) const float global_float;
 
 // FP32 chain of one lane. Factors are e = em * 2^en, with en = 0 except for
 // lower-tail factors below 2^-60 (t < -9.1), which keep 2^floor(-v^2) in en so
@@ -176,22 +158,27 @@ __device__ __forceinline__ void item_f32(const Item& it, const Aux32* __restrict
                                          const uint64_t* __restrict__ Zg, double* __restrict__ sums) {
   const InstDesc& I = *it.I;
   const int lane = threadIdx.x & 63;
-  global_float* __restrict__ prep = (global_float*)(reinterpret_cast<const float*>(I.prep) + it.i * I.prep_stride);
+  const float* __restrict__ prep = reinterpret_cast<const float*>(I.prep) + it.i * I.prep_stride;
   const Aux32 ax = aux32[it.t];
   const bool split0 = uniform(ax.en0 != 0.0f) != 0;
   const int p_begin = 1 + it.c * I.chunk_points;
   const int p_last = min(I.n_points, p_begin + I.chunk_points - 1);
-  // the lane's chain starts at point p_begin + lane and strides 64
-  uint64_t U[K], st[K];
+  // the lane's chain starts at point p_begin + lane and strides 64: U_j += 64 Z_j
+  // per iteration, with Z_j re-read (scalar load) in the loop so the K steps do
+  // not occupy 2K SGPRs across it
+  uint64_t U[K];
 #pragma unroll
   for (int j = 0; j < K; ++j) {
     const uint64_t S = lattice_shift(I.seed, it.i, it.r, j);
-    st[j] = Zg[j] * 64u;
     U[j] = (uint64_t)(p_begin + lane) * Zg[j] + S;
   }
+  constexpr int kRowElems = (K + 1) * (K + 2) / 2;   // rows 0..K of the term's block
+  __shared__ float srow[kRowElems];
+  for (int e = lane; e < kRowElems; e += 64) srow[e] = prep[e];
+  __syncthreads();
   double acc_num = 0.0, acc_den = 0.0, acc_cnum = 0.0;
   for (int p0 = p_begin; p0 <= p_last; p0 += 64) {
-    // compiler-only barrier: the term's rows are re-read (L1 hits) in every
+    // compiler-only barrier: the term's rows are re-read from LDS in every
     // iteration instead of being held in K(K+3)/2 registers across the loop
     __asm__ volatile("" ::: "memory");
     float y[K];
@@ -202,9 +189,9 @@ __device__ __forceinline__ void item_f32(const Item& it, const Aux32* __restrict
     int qe = 0;
 #pragma unroll
     for (int a = 1; a <= K; ++a) {
-      global_float* row = prep + a * (a + 1) / 2;
+      const int ro = a * (a + 1) / 2;
       const CoordF32 wp = lattice_coord_f32((uint32_t)(U[a - 1] >> 32));
-      U[a - 1] += st[a - 1];
+      U[a - 1] += Zg[a - 1] << 6;
       // y = Phi^{-1}(u), u = w e; u <= 1/2 whenever the previous t <= 0, and
       // otherwise 1 - u = (1 - w) + w (1 - e) keeps its digits
       const float um = wp.w * em;
@@ -218,9 +205,9 @@ __device__ __forceinline__ void item_f32(const Item& it, const Aux32* __restrict
         split = false;
       }
       y[a - 1] = lower ? -z : z;
-      float v = row[a];
+      float v = srow[ro + a];
 #pragma unroll
-      for (int c = 0; c < a; ++c) v = fmaf(-row[c], y[c], v);
+      for (int c = 0; c < a; ++c) v = fmaf(-srow[ro + c], y[c], v);
       const PhiParts ph = phi_f32(v);
       em = ph.em;
       m = ph.m;
@@ -270,17 +257,20 @@ __device__ __forceinline__ void item_f32(const Item& it, const Aux32* __restrict
   }
 }
 
+// Minimum waves per SIMD requested per chain size K: the largest value at which
+// the unrolled chain still compiles without spilling (measured on gfx950; the
+// hint only caps registers, so chains that fit more waves keep them).
+constexpr int f32_min_waves(int K) { return K <= 30 ? 4 : 3; }
+constexpr int f64_min_waves(int K) { return K <= 11 ? 4 : K <= 18 ? 3 : 2; }
+
 template <int K>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void qmc_f64(
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(f64_min_waves(K)))) void qmc_f64(
     const InstDesc* __restrict__ insts, const RangeDesc* __restrict__ ranges, int n_ranges,
     const Aux64* __restrict__ aux64, const uint64_t* __restrict__ Zg, double* __restrict__ sums) {
   const Item it = decode_item(insts, ranges, n_ranges, (int64_t)blockIdx.x);
   item_f64<K>(it, aux64, Zg, sums);
 }
 
-// Minimum waves per SIMD requested for the FP32 chain of size K (caps the
-// registers of the unrolled chain; chosen so that no K spills).
-constexpr int f32_min_waves(int K) { return K <= 8 ? 8 : K <= 10 ? 6 : K <= 13 ? 5 : K <= 19 ? 4 : K <= 25 ? 3 : 2; }
 
 template <int K>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(f32_min_waves(K)))) void qmc_f32(
