@@ -11,7 +11,8 @@
 //            of it can get closer (every other point is already within l of
 //            the set), so only the grid cells meeting that disc are visited;
 //            an indexed max-heap keyed by (d^2 desc, index asc) gives the next
-//            point.
+//            point. Points are kept in grid-cell order so a visit streams
+//            contiguous memory.
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
@@ -34,43 +35,49 @@ inline double sqd(double ax, double ay, double bx, double by) {
   return xx + yy;
 }
 
-// Indexed binary max-heap over point ids with keys that only decrease.
+// Indexed binary max-heap over slots whose keys only decrease; ties rank the
+// lower original index first.
 struct MaxHeap {
-  std::vector<int64_t> heap;   // heap position -> point
-  std::vector<int64_t> pos;    // point -> heap position, -1 when removed
-  const std::vector<double>* key;
+  std::vector<int32_t> heap;   // heap position -> slot
+  std::vector<int32_t> pos;    // slot -> heap position
+  const double* key = nullptr;
+  const int32_t* id = nullptr; // slot -> original index (tie-break)
 
-  bool before(int64_t a, int64_t b) const {   // a ranks above b
-    const double ka = (*key)[a], kb = (*key)[b];
-    return ka > kb || (ka == kb && a < b);
+  bool before(int32_t a, int32_t b) const {   // a ranks above b
+    const double ka = key[a], kb = key[b];
+    return ka > kb || (ka == kb && id[a] < id[b]);
   }
-  void swap_at(int64_t i, int64_t j) {
-    std::swap(heap[i], heap[j]);
-    pos[heap[i]] = i;
-    pos[heap[j]] = j;
-  }
-  void sift_down(int64_t i) {
-    const int64_t n = (int64_t)heap.size();
+  void sift_down(int32_t i) {
+    const int32_t n = (int32_t)heap.size();
+    const int32_t v = heap[i];
     for (;;) {
-      int64_t b = i;
-      const int64_t l = 2 * i + 1, r = 2 * i + 2;
-      if (l < n && before(heap[l], heap[b])) b = l;
-      if (r < n && before(heap[r], heap[b])) b = r;
-      if (b == i) return;
-      swap_at(i, b);
+      const int32_t l = 2 * i + 1;
+      if (l >= n) break;
+      int32_t b = l;
+      if (l + 1 < n && before(heap[l + 1], heap[l])) b = l + 1;
+      if (!before(heap[b], v)) break;
+      heap[i] = heap[b];
+      pos[heap[i]] = i;
       i = b;
     }
+    heap[i] = v;
+    pos[v] = i;
   }
-  void build(const std::vector<int64_t>& items) {
-    heap = items;
-    for (int64_t i = 0; i < (int64_t)heap.size(); ++i) pos[heap[i]] = i;
-    for (int64_t i = (int64_t)heap.size() / 2 - 1; i >= 0; --i) sift_down(i);
+  // every slot except the one holding original index `skip`
+  void build(int32_t n, int64_t skip) {
+    heap.clear();
+    heap.reserve(n);
+    pos.assign(n, -1);
+    for (int32_t q = 0; q < n; ++q)
+      if (id[q] != skip) heap.push_back(q);
+    for (int32_t i = 0; i < (int32_t)heap.size(); ++i) pos[heap[i]] = i;
+    for (int32_t i = (int32_t)heap.size() / 2 - 1; i >= 0; --i) sift_down(i);
   }
-  int64_t pop() {
-    const int64_t top = heap[0];
-    swap_at(0, (int64_t)heap.size() - 1);
+  int32_t pop() {
+    const int32_t top = heap[0];
+    heap[0] = heap.back();
+    pos[heap[0]] = 0;
     heap.pop_back();
-    pos[top] = -1;
     if (!heap.empty()) sift_down(0);
     return top;
   }
@@ -111,65 +118,63 @@ void order_maxmin(const double* locs, int64_t D, int64_t* perm) {
   perm[0] = first;
   if (D == 1) return;
 
-  // uniform grid of about 2 points per cell over the bounding box
+  // Uniform grid of about 2 points per cell over the bounding box; the points
+  // are copied into cell order ("slots") so that a cell's points are contiguous.
   const int64_t G = std::max<int64_t>(1, (int64_t)std::sqrt((double)D / 2.0));
   const double wx = (x1 - x0) > 0 ? (x1 - x0) / (double)G : 1.0;
   const double wy = (y1 - y0) > 0 ? (y1 - y0) / (double)G : 1.0;
-  auto cell_of = [&](double v, double lo, double w) {
-    int64_t c = (int64_t)std::floor((v - lo) / w);
-    return std::min<int64_t>(std::max<int64_t>(c, 0), G - 1);
-  };
-  std::vector<int64_t> start(G * G + 1, 0), items(D);
-  std::vector<int64_t> cx_of(D), cy_of(D);
+  auto cell_x = [&](double v) { return std::min<int64_t>(std::max<int64_t>((int64_t)std::floor((v - x0) / wx), 0), G - 1); };
+  auto cell_y = [&](double v) { return std::min<int64_t>(std::max<int64_t>((int64_t)std::floor((v - y0) / wy), 0), G - 1); };
+  std::vector<int32_t> start(G * G + 1, 0);
+  std::vector<int32_t> cell(D);
   for (int64_t j = 0; j < D; ++j) {
-    cx_of[j] = cell_of(locs[2 * j], x0, wx);
-    cy_of[j] = cell_of(locs[2 * j + 1], y0, wy);
-    ++start[cx_of[j] * G + cy_of[j] + 1];
+    cell[j] = (int32_t)(cell_x(locs[2 * j]) * G + cell_y(locs[2 * j + 1]));
+    ++start[cell[j] + 1];
   }
   for (int64_t c = 0; c < G * G; ++c) start[c + 1] += start[c];
+  std::vector<double> px(D), py(D), mind2(D);
+  std::vector<int32_t> id(D);
   {
-    std::vector<int64_t> fillp(start.begin(), start.end() - 1);
-    for (int64_t j = 0; j < D; ++j) items[fillp[cx_of[j] * G + cy_of[j]]++] = j;
+    std::vector<int32_t> fill(start.begin(), start.end() - 1);
+    for (int64_t j = 0; j < D; ++j) {
+      const int32_t q = fill[cell[j]]++;
+      px[q] = locs[2 * j];
+      py[q] = locs[2 * j + 1];
+      id[q] = (int32_t)j;
+    }
   }
-
-  std::vector<double> mind2(D);
-  std::vector<char> taken(D, 0);
+  // a selected slot's key is -inf: no distance is below it, and it is never
+  // compared again
   const double fx = locs[2 * first], fy = locs[2 * first + 1];
-  for (int64_t j = 0; j < D; ++j) mind2[j] = sqd(locs[2 * j], locs[2 * j + 1], fx, fy);
-  taken[first] = 1;
+  for (int64_t q = 0; q < D; ++q) mind2[q] = id[q] == first ? -INFINITY : sqd(px[q], py[q], fx, fy);
   MaxHeap h;
-  h.key = &mind2;
-  h.pos.assign(D, -1);
-  {
-    std::vector<int64_t> rest;
-    rest.reserve(D - 1);
-    for (int64_t j = 0; j < D; ++j)
-      if (j != first) rest.push_back(j);
-    h.build(rest);
-  }
+  h.key = mind2.data();
+  h.id = id.data();
+  h.build((int32_t)D, first);
+  // a point can only move closer to the set through the newly selected point s
+  // if its distance to s is below l = sqrt(mind2[s]) (every other point is
+  // already within l of the set); the cells meeting the disc of radius l' > l
+  // are visited, l' enlarged by a relative and an absolute margin against the
+  // rounding of the cell bounds
+  const double span = std::max(std::max(std::fabs(x0), std::fabs(x1)), std::max(std::fabs(y0), std::fabs(y1)));
+  const double abs_margin = 8.0 * span * std::numeric_limits<double>::epsilon();
   for (int64_t t = 1; t < D; ++t) {
-    const int64_t s = h.pop();
-    perm[t] = s;
-    taken[s] = 1;
-    const double sx = locs[2 * s], sy = locs[2 * s + 1];
-    // Points with d(j, s) >= l cannot improve (mind2[j] <= l^2). Visit the cells
-    // meeting the disc of radius l (plus one cell of margin against rounding).
-    const double l = std::sqrt(mind2[s]) * (1.0 + 1e-12);
-    const int64_t ax = std::max<int64_t>(0, (int64_t)std::floor((sx - l - x0) / wx) - 1);
-    const int64_t bx = std::min<int64_t>(G - 1, (int64_t)std::floor((sx + l - x0) / wx) + 1);
-    const int64_t ay = std::max<int64_t>(0, (int64_t)std::floor((sy - l - y0) / wy) - 1);
-    const int64_t by = std::min<int64_t>(G - 1, (int64_t)std::floor((sy + l - y0) / wy) + 1);
+    const int32_t s = h.pop();
+    perm[t] = id[s];
+    const double l2 = mind2[s];
+    mind2[s] = -INFINITY;
+    if (!(l2 > 0.0)) continue;   // duplicates of selected points: nothing can improve
+    const double sx = px[s], sy = py[s];
+    const double l = std::sqrt(l2) * (1.0 + 1e-9) + abs_margin;
+    const int64_t ax = cell_x(sx - l), bx = cell_x(sx + l);
+    const int64_t ay = cell_y(sy - l), by = cell_y(sy + l);
     for (int64_t gx = ax; gx <= bx; ++gx) {
-      for (int64_t gy = ay; gy <= by; ++gy) {
-        const int64_t c = gx * G + gy;
-        for (int64_t q = start[c]; q < start[c + 1]; ++q) {
-          const int64_t j = items[q];
-          if (taken[j]) continue;
-          const double d = sqd(locs[2 * j], locs[2 * j + 1], sx, sy);
-          if (d < mind2[j]) {
-            mind2[j] = d;
-            h.sift_down(h.pos[j]);
-          }
+      const int32_t q0 = start[gx * G + ay], q1 = start[gx * G + by + 1];   // cells (gx, ay..by) are contiguous
+      for (int32_t q = q0; q < q1; ++q) {
+        const double d = sqd(px[q], py[q], sx, sy);
+        if (d < mind2[q]) {
+          mind2[q] = d;
+          h.sift_down(h.pos[q]);
         }
       }
     }

@@ -35,7 +35,7 @@ def test_struct_layouts_match_header():
 
 
 @pytest.mark.parametrize("rule", [W.ORDER_COORD, W.ORDER_MAXMIN])
-@pytest.mark.parametrize("case", ["grid", "uniform", "dupes", "line"])
+@pytest.mark.parametrize("case", ["grid", "uniform", "dupes", "line", "repeated", "thin_offset"])
 def test_host_ordering_matches_oracle(rule, case):
     rng = np.random.default_rng(11)
     if case == "grid":
@@ -44,6 +44,10 @@ def test_host_ordering_matches_oracle(rule, case):
         locs = rng.random((3000, 2))
     elif case == "dupes":
         locs = np.round(rng.random((500, 2)) * 6) / 6.0
+    elif case == "repeated":           # every location three times
+        locs = np.repeat(rng.random((40, 2)), 3, axis=0)
+    elif case == "thin_offset":        # a strip far from the origin (cell bounds at large magnitude)
+        locs = rng.random((500, 2)) * np.array([1e-6, 1.0]) + 1e3
     else:
         locs = np.stack([np.linspace(0, 1, 300), np.full(300, 0.25)], axis=1)
     got = V.vecchia_order(locs, rule)
