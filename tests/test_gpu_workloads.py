@@ -137,3 +137,42 @@ def test_uniform250k_tail_instance():
     assert abs(out32[0] - out64[0]) <= FP32_REL_TOL * abs(out64[0])
     assert np.max(np.abs(t32[:, 0] - t64[:, 0])) <= FP32_TERM_TOL
     V.vecchia_plan_destroy(plan)
+
+
+def test_serving_mix_equals_standalone_calls():
+    # requests shaped like the serving stream (mixed D and m, per-request
+    # covariance range and scale factor, 2048-8192 points) submitted together;
+    # every result must equal the same request evaluated alone, bitwise
+    import time
+    torch = torch_cuda()
+    from paper_2007_15195_amd import vecchia as V
+    st = W.serving_stream(n_plans=5, n_requests=30, d_min=1000, d_max=20000)
+    plans = [V.vecchia_plan(p.locs, p.ordering, p.m, p.cov) for p in st.plans]
+    xs = [torch.tensor(r.x, dtype=torch.float64, device="cuda") for r in st.requests]
+    torch.cuda.synchronize()
+    alone = []
+    out = torch.empty(2, dtype=torch.float64, device="cuda")
+    for r, x in zip(st.requests, xs):
+        V.vecchia_logcdf(plans[r.plan_id], x, V.as_qmc(r.qmc), out, scale=r.scale, cov_override=r.cov)
+        torch.cuda.synchronize()
+        alone.append(out.cpu().numpy().copy())
+    srv = V.vecchia_server_create(4 << 30, 8)
+    tickets = [V.vecchia_submit(srv, plans[r.plan_id], x, r.qmc, scale=r.scale, cov_override=r.cov)
+               for r, x in zip(st.requests, xs)]
+    got = {}
+    t_end = time.time() + 120
+    while len(got) < len(tickets) and time.time() < t_end:
+        for k, t in enumerate(tickets):
+            if k not in got:
+                res = V.vecchia_poll(srv, t)
+                if res is not None:
+                    got[k] = res
+        time.sleep(0.001)
+    V.vecchia_server_destroy(srv)
+    assert len(got) == len(tickets)
+    for k, (lf, se, lat) in got.items():
+        assert lf == alone[k][0] and se == alone[k][1], k
+        assert np.isfinite(lf) and lf < 0 and lat > 0
+    print("requests", len(tickets), "m values", sorted({st.plans[r.plan_id].m for r in st.requests}), flush=True)
+    for p in plans:
+        V.vecchia_plan_destroy(p)
