@@ -38,8 +38,8 @@ __device__ __forceinline__ double wave_sum(double v) {
 __global__ __launch_bounds__(64 * kFinalizeWaves) void term_finalize(
     const InstDesc* __restrict__ insts, int n_inst, const int64_t* __restrict__ term_bases,
     int64_t total_terms, const Aux64* __restrict__ aux64, const double* __restrict__ sums,
-    double2* __restrict__ term_res) {
-  const int64_t t = (int64_t)blockIdx.x * kFinalizeWaves + (threadIdx.x >> 6);
+    double2* __restrict__ term_res, int64_t term_base) {
+  const int64_t t = term_base + (int64_t)blockIdx.x * kFinalizeWaves + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (t >= total_terms) return;   // t is the same on every lane of a wave
   const int ii = find_inst(term_bases, n_inst, t);
@@ -93,10 +93,11 @@ __global__ __launch_bounds__(64 * kFinalizeWaves) void term_finalize(
 }
 
 __global__ __launch_bounds__(kFinalizeThreads) void instance_logsum(const InstDesc* __restrict__ insts,
-                                                                     const double2* __restrict__ term_res) {
+                                                                     const double2* __restrict__ term_res,
+                                                                     int64_t inst_base) {
   __shared__ double red_lt[kFinalizeThreads];
   __shared__ double red_se[kFinalizeThreads];
-  const InstDesc& I = insts[blockIdx.x];
+  const InstDesc& I = insts[inst_base + (int64_t)blockIdx.x];
   const double2* r = term_res + I.term_base;
   double part_lt = 0.0, part_se = 0.0;
   for (int64_t i = threadIdx.x; i < I.D; i += kFinalizeThreads) {
@@ -126,14 +127,23 @@ hipError_t launch_finalize(const InstDesc* d_insts, int n_inst, const int64_t* d
                            int64_t total_terms, const Aux64* aux64, const double* sums,
                            double2* term_res, hipStream_t s) {
   if (n_inst <= 0) return hipSuccess;
-  const int64_t blocks = (total_terms + kFinalizeWaves - 1) / kFinalizeWaves;
-  if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(term_finalize, dim3((unsigned)blocks), dim3(64 * kFinalizeWaves), 0, s, d_insts, n_inst,
-                     d_term_bases, total_terms, aux64, sums, term_res);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(instance_logsum, dim3((unsigned)n_inst), dim3(kFinalizeThreads), 0, s, d_insts, term_res);
-  return hipGetLastError();
+  constexpr int64_t kPer = kMaxLaunchThreads / 64;   // terms (one wave each) per launch
+  for (int64_t b = 0; b < total_terms; b += kPer) {
+    const int64_t n = total_terms - b < kPer ? total_terms - b : kPer;
+    const unsigned blocks = (unsigned)((n + kFinalizeWaves - 1) / kFinalizeWaves);
+    hipLaunchKernelGGL(term_finalize, dim3(blocks), dim3(64 * kFinalizeWaves), 0, s, d_insts, n_inst,
+                       d_term_bases, total_terms, aux64, sums, term_res, b);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  constexpr int64_t kPerInst = kMaxLaunchThreads / kFinalizeThreads;   // instances (one block each) per launch
+  for (int64_t b = 0; b < n_inst; b += kPerInst) {
+    const unsigned n = (unsigned)(n_inst - b < kPerInst ? n_inst - b : kPerInst);
+    hipLaunchKernelGGL(instance_logsum, dim3(n), dim3(kFinalizeThreads), 0, s, d_insts, term_res, b);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace vecchia

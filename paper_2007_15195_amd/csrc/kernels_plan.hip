@@ -22,12 +22,12 @@ template <int M>
 __global__ __launch_bounds__(64 * kKnnWaves) void knn_preceding(const double* __restrict__ xs,
                                                                 const double* __restrict__ ys, int64_t D,
                                                                 int32_t* __restrict__ nbr,
-                                                                int32_t* __restrict__ kcnt) {
+                                                                int32_t* __restrict__ kcnt, int64_t q_base) {
 #pragma clang fp contract(off)
   __shared__ double2 tile[kKnnTile];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int64_t q0 = (int64_t)blockIdx.x * kKnnWaves;
+  const int64_t q0 = q_base + (int64_t)blockIdx.x * kKnnWaves;
   const int64_t i = q0 + wave;
   const bool valid = i < D;
   const double qx = valid ? xs[i] : 0.0;
@@ -112,9 +112,15 @@ __global__ void fill_i32(int32_t* p, int64_t n, int32_t v) {
 template <int M>
 hipError_t knn_dispatch(const double* xs, const double* ys, int64_t D, int32_t* nbr, int32_t* kcnt,
                         hipStream_t s) {
-  const unsigned blocks = (unsigned)((D + kKnnWaves - 1) / kKnnWaves);
-  hipLaunchKernelGGL(knn_preceding<M>, dim3(blocks), dim3(64 * kKnnWaves), 0, s, xs, ys, D, nbr, kcnt);
-  return hipGetLastError();
+  constexpr int64_t kPer = kMaxLaunchThreads / 64;   // queries (one wave each) per launch
+  for (int64_t b = 0; b < D; b += kPer) {
+    const int64_t n = D - b < kPer ? D - b : kPer;
+    const unsigned blocks = (unsigned)((n + kKnnWaves - 1) / kKnnWaves);
+    hipLaunchKernelGGL(knn_preceding<M>, dim3(blocks), dim3(64 * kKnnWaves), 0, s, xs, ys, D, nbr, kcnt, b);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 template <int... Ms>

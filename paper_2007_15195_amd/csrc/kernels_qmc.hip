@@ -266,8 +266,9 @@ constexpr int f64_min_waves(int K) { return K <= 11 ? 4 : K <= 18 ? 3 : 2; }
 template <int K>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(f64_min_waves(K)))) void qmc_f64(
     const InstDesc* __restrict__ insts, const RangeDesc* __restrict__ ranges, int n_ranges,
-    const Aux64* __restrict__ aux64, const uint64_t* __restrict__ Zg, double* __restrict__ sums) {
-  const Item it = decode_item(insts, ranges, n_ranges, (int64_t)blockIdx.x);
+    const Aux64* __restrict__ aux64, const uint64_t* __restrict__ Zg, double* __restrict__ sums,
+    int64_t item_base) {
+  const Item it = decode_item(insts, ranges, n_ranges, item_base + (int64_t)blockIdx.x);
   item_f64<K>(it, aux64, Zg, sums);
 }
 
@@ -277,8 +278,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(f32_min_wave
     const InstDesc* __restrict__ insts,
                                               const RangeDesc* __restrict__ ranges, int n_ranges,
                                               const Aux32* __restrict__ aux32,
-                                              const uint64_t* __restrict__ Zg, double* __restrict__ sums) {
-  const Item it = decode_item(insts, ranges, n_ranges, (int64_t)blockIdx.x);
+                                              const uint64_t* __restrict__ Zg, double* __restrict__ sums,
+                                              int64_t item_base) {
+  const Item it = decode_item(insts, ranges, n_ranges, item_base + (int64_t)blockIdx.x);
   item_f32<K>(it, aux32, Zg, sums);
 }
 
@@ -287,13 +289,17 @@ hipError_t qmc_dispatch(int precision, const InstDesc* insts, const RangeDesc* r
                         int64_t n_items, const Aux64* aux64, const Aux32* aux32, const uint64_t* Z,
                         double* sums, hipStream_t s) {
   if (n_items > 0x7fffffffLL) return hipErrorInvalidValue;
-  if (precision == VECCHIA_FP32_LOOP)
-    hipLaunchKernelGGL(qmc_f32<K>, dim3((unsigned)n_items), dim3(64), 0, s, insts, ranges, n_ranges,
-                       aux32, Z, sums);
-  else
-    hipLaunchKernelGGL(qmc_f64<K>, dim3((unsigned)n_items), dim3(64), 0, s, insts, ranges, n_ranges,
-                       aux64, Z, sums);
-  return hipGetLastError();
+  constexpr int64_t kPer = kMaxLaunchThreads / 64;   // items (one wave each) per launch
+  for (int64_t b = 0; b < n_items; b += kPer) {
+    const unsigned n = (unsigned)(n_items - b < kPer ? n_items - b : kPer);
+    if (precision == VECCHIA_FP32_LOOP)
+      hipLaunchKernelGGL(qmc_f32<K>, dim3(n), dim3(64), 0, s, insts, ranges, n_ranges, aux32, Z, sums, b);
+    else
+      hipLaunchKernelGGL(qmc_f64<K>, dim3(n), dim3(64), 0, s, insts, ranges, n_ranges, aux64, Z, sums, b);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 template <int... Ks>

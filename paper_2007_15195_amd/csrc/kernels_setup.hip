@@ -39,13 +39,13 @@ __device__ __forceinline__ int find_inst(const int64_t* __restrict__ bases, int 
 __global__ __launch_bounds__(64) void term_setup(const InstDesc* __restrict__ insts, int n_inst,
                                                  const int64_t* __restrict__ term_bases,
                                                  Aux64* __restrict__ aux64,
-                                                 Aux32* __restrict__ aux32) {
+                                                 Aux32* __restrict__ aux32, int64_t term_base) {
   __shared__ double C[kMaxVars][kMaxVars + 1];
   __shared__ double px[kMaxVars], py[kMaxVars], pb[kMaxVars];
   __shared__ int pv[kMaxVars];
   __shared__ double piv;
   const int lane = threadIdx.x;
-  const int64_t t = blockIdx.x;
+  const int64_t t = term_base + (int64_t)blockIdx.x;
   const int ii = find_inst(term_bases, n_inst, t);
   const InstDesc& I = insts[ii];
   const int64_t i = t - term_bases[ii];
@@ -143,9 +143,14 @@ hipError_t launch_setup(const InstDesc* d_insts, int n_inst, const int64_t* d_te
                         int64_t total_terms, Aux64* aux64, Aux32* aux32, hipStream_t s) {
   if (total_terms <= 0) return hipSuccess;
   if (total_terms > 0x7fffffffLL) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(term_setup, dim3((unsigned)total_terms), dim3(64), 0, s, d_insts, n_inst,
-                     d_term_bases, aux64, aux32);
-  return hipGetLastError();
+  constexpr int64_t kPer = kMaxLaunchThreads / 64;   // terms (one wave each) per launch
+  for (int64_t b = 0; b < total_terms; b += kPer) {
+    const unsigned n = (unsigned)(total_terms - b < kPer ? total_terms - b : kPer);
+    hipLaunchKernelGGL(term_setup, dim3(n), dim3(64), 0, s, d_insts, n_inst, d_term_bases, aux64, aux32, b);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace vecchia

@@ -11,6 +11,9 @@ namespace vecchia {
 constexpr int kMaxM = VECCHIA_MAX_M;   // conditioning-set size limit
 constexpr int kMaxVars = kMaxM + 1;    // variables per term
 constexpr int kFinalizeThreads = 256;
+// A launch may hold fewer than 2^32 work-items in total; per-term and per-item
+// kernels are split into launches of at most this many threads.
+constexpr int64_t kMaxLaunchThreads = (int64_t)1 << 31;
 
 // One log-CDF instance of a launch (device-resident descriptor).
 struct InstDesc {

@@ -176,3 +176,37 @@ def test_serving_mix_equals_standalone_calls():
     print("requests", len(tickets), "m values", sorted({st.plans[r.plan_id].m for r in st.requests}), flush=True)
     for p in plans:
         V.vecchia_plan_destroy(p)
+
+
+def test_launch_split_beyond_the_work_item_limit():
+    # 64-point chunks on 70,000 terms x 8 shifts x 4096 points give 35.8M work
+    # items (one wave each): more than one launch can hold (2^32 work-items), so
+    # the QMC launch is split; the result must match the default chunking up to
+    # the FP64 regrouping of the partial sums
+    torch = torch_cuda()
+    from paper_2007_15195_amd import vecchia as V
+    rng = np.random.default_rng(90)
+    D, m = 70_000, 5
+    locs = rng.random((D, 2))
+    cov = V.make_cov(V.VECCHIA_COV_MATERN, 1.5, 1.0, 0.05, 1e-8)
+    x = torch.tensor(rng.normal(1.5, 0.5, D), dtype=torch.float64, device="cuda")
+    q = V.make_qmc(4096, 8, 91, V.VECCHIA_FP32_LOOP)
+    res = []
+    try:
+        for chunk in (0, 64):
+            V.vecchia_tuning_set(V.VECCHIA_FP32_LOOP, m, chunk)
+            plan = V.vecchia_plan(locs, W.ORDER_COORD, m, cov)
+            out = torch.empty(2, dtype=torch.float64, device="cuda")
+            terms = torch.empty((D, 2), dtype=torch.float64, device="cuda")
+            V.vecchia_logcdf(plan, x, q, out, terms=terms)
+            torch.cuda.synchronize()
+            assert V.vecchia_plan_status(plan) == -1
+            res.append((out.cpu().numpy(), terms.cpu().numpy()))
+            V.vecchia_plan_destroy(plan)
+    finally:
+        V.vecchia_tuning_set(V.VECCHIA_FP32_LOOP, m, 0)
+    (o1, t1), (o2, t2) = res
+    print("logF", o1[0], o2[0], flush=True)
+    assert np.all(np.isfinite(t2[:, 0]))
+    assert np.max(np.abs(t1[:, 0] - t2[:, 0])) <= 1e-12
+    assert abs(o1[0] - o2[0]) <= 1e-11 * abs(o1[0])
