@@ -51,6 +51,9 @@ SLOTS_PER_STEP_F32_K10 = 48.2
 # MI355X FP32 vector peak 157.3 TFLOP/s = 256 CUs x 2.4 GHz x 128 FMA lanes x 2:
 # 78.64e12 full-rate VALU lane-slots per second.
 VALU_PEAK_TSLOTS = 256 * 2.4e9 * 128 / 1e12
+# Transcendental instructions per SOV step on that path (the rest are full-rate):
+# Phi^-1 takes a log2, a sqrt and a reciprocal, Phi a reciprocal and an exp2.
+TRANS_PER_STEP = {"exp": 1, "log": 1, "rcp": 2, "sqrt": 1}
 # HBM bytes per launch of qmc_f32<10> from rocprofv3 FETCH_SIZE x 2.0 +
 # WRITE_SIZE x 1.0 (factors from a 256 MiB copy); None once the kernel changes.
 TRAFFIC_BYTES_F32_K10 = 12.19e6
@@ -357,6 +360,13 @@ def main():
     t32, t64 = terms32.cpu().numpy(), terms64.cpu().numpy()
     V.vecchia_plan_destroy(plan)
 
+    # measured issue rates (wave64 instructions per CU per ns) and the ceiling
+    # they give this kernel's instruction mix
+    rates = V.vecchia_calibrate_valu(stream=sp)
+    n_trans = sum(TRANS_PER_STEP.values())
+    ns_per_wave_step = ((SLOTS_PER_STEP_F32_K10 - n_trans) / rates["fma"] +
+                        sum(c / rates[k] for k, c in TRANS_PER_STEP.items()))
+    ceiling = SLOTS_PER_STEP_F32_K10 * 64 * 256 / ns_per_wave_step / 1e3   # T lane-slots/s
     kernel_avg_ms = k_ms / max(k_launches, 1)
     steps_per_launch = k_steps / max(k_launches, 1)
     achieved = steps_per_launch * SLOTS_PER_STEP_F32_K10 / (kernel_avg_ms * 1e-3) / 1e12
@@ -390,7 +400,9 @@ def main():
                      "achieved": achieved, "peak": VALU_PEAK_TSLOTS, "unit": "T VALU-slots/s",
                      "frac": achieved / VALU_PEAK_TSLOTS, "traffic": TRAFFIC_BYTES_F32_K10,
                      "avg_launch_ms": kernel_avg_ms, "sov_steps_per_launch": steps_per_launch,
-                     "slots_per_step": SLOTS_PER_STEP_F32_K10},
+                     "slots_per_step": SLOTS_PER_STEP_F32_K10,
+                     "measured_rates_wave_instr_per_cu_ns": {k: round(v, 4) for k, v in rates.items()},
+                     "measured_ceiling": ceiling, "frac_of_measured_ceiling": achieved / ceiling},
     }
     if tuned is not None:
         res["autotune"] = tuned

@@ -215,6 +215,15 @@ vecchia_status vecchia_autotune(int32_t precision, int32_t n_points, int32_t n_s
 vecchia_status vecchia_tuning_get(int32_t precision, int32_t m, int32_t* chunk_points);
 vecchia_status vecchia_tuning_set(int32_t precision, int32_t m, int32_t chunk_points);
 
+/* Measurement hook for the roofline: measured issue rates of the vector ALU on
+ * the current device, in wave64 instructions per compute unit per nanosecond,
+ * for a full-rate FP32 FMA and for v_exp_f32, v_log_f32, v_rcp_f32 and
+ * v_sqrt_f32 (rates_out[0..4], host memory). Each rate comes from a kernel of
+ * independent dependency chains over many waves per CU, timed with HIP events
+ * on hip_stream (best of three). Synchronises hip_stream. Errors: INVALID
+ * (rates_out NULL), HIP. */
+vecchia_status vecchia_calibrate_valu(void* hip_stream, double* rates_out);
+
 /* Serving: a request loop with continuous batching. Requests are admitted in
  * arrival order while their workspace fits in hbm_budget_bytes and one of
  * max_slots execution slots (each its own stream) is free; admitted requests

@@ -31,6 +31,7 @@ SOURCES = [
     "api.cpp",
     "host_order.cpp",
     "autotune.cpp",
+    "calibrate.hip",
 ]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-function",

@@ -31,7 +31,7 @@ EXPORTED = [
     "vecchia_plan_destroy", "vecchia_batch_create", "vecchia_batch_logcdf", "vecchia_batch_status",
     "vecchia_batch_destroy", "vecchia_server_create", "vecchia_submit", "vecchia_poll",
     "vecchia_server_destroy", "vecchia_profile_enable", "vecchia_profile_read", "vecchia_profile_reset",
-    "vecchia_autotune", "vecchia_tuning_get", "vecchia_tuning_set",
+    "vecchia_autotune", "vecchia_tuning_get", "vecchia_tuning_set", "vecchia_calibrate_valu",
 ]
 
 
@@ -91,6 +91,7 @@ def lib():
         "vecchia_autotune": [c_int32, c_int32, c_int32, c_void_p, c_int32, c_void_p, c_void_p, c_void_p],
         "vecchia_tuning_get": [c_int32, c_int32, POINTER(c_int32)],
         "vecchia_tuning_set": [c_int32, c_int32, c_int32],
+        "vecchia_calibrate_valu": [c_void_p, c_void_p],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -326,3 +327,10 @@ def vecchia_tuning_get(precision: int, m: int) -> int:
 
 def vecchia_tuning_set(precision: int, m: int, chunk_points: int) -> None:
     _check(lib().vecchia_tuning_set(int(precision), int(m), int(chunk_points)))
+
+
+def vecchia_calibrate_valu(stream=None) -> dict:
+    """Measured wave64 instructions per CU per ns: fma, exp, log, rcp, sqrt."""
+    r = (c_double * 5)()
+    _check(lib().vecchia_calibrate_valu(_stream_ptr(stream), ctypes.cast(r, c_void_p)))
+    return dict(zip(("fma", "exp", "log", "rcp", "sqrt"), list(r)))

@@ -118,3 +118,9 @@ def test_tuning_table_and_autotune_validation():
         with pytest.raises(V.VecchiaError) as e:
             V.vecchia_autotune(*bad, stream=0)
         assert e.value.status == 1
+
+
+def test_calibration_hook_rejects_missing_output():
+    with pytest.raises(V.VecchiaError) as e:
+        V._check(V.lib().vecchia_calibrate_valu(None, None))
+    assert e.value.status == 1
