@@ -1,6 +1,6 @@
 """Benchmark of the Vecchia log-CDF hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--sections c1,c2,c3,c4,c5]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--sections c1,c2,c3,c4,c5,mix]
 
 Headline workload (the JSON line's value): D = 2,500 locations uniform in
 [0,1]^2, Matern nu = 3/2 (range 0.1, nugget 1e-8), maxmin ordering, m = 10,
@@ -26,7 +26,9 @@ baseline on a bounded sample, and one object per further workload:
   c5_serving  mixed requests (D in [1000, 100000], m in 5..30, per-request
               range and scale factor, 2048-8192 x 8 points) through the serving
               loop: capacity with every request queued at once, then Poisson
-              arrivals at 80 % of it with p50/p99 latency.
+              arrivals at 80 % of it with p50/p99 latency;
+  scale_mixture  the scale-mixture CDF E Phi_D(x / R), R Pareto(2), on the headline
+              geometry (34 evaluations per call: 2 first-pass + 32 nodes).
 The launch shape of each workload is set by vecchia_autotune beforehand.
 """
 from __future__ import annotations
@@ -71,7 +73,7 @@ def parse():
     ap.add_argument("--cpu-terms", type=int, default=500)
     ap.add_argument("--fp32-only", action="store_true",
                     help="time the full FP32 step only (short runs under a profiler)")
-    ap.add_argument("--sections", default="c1,c2,c3,c4,c5",
+    ap.add_argument("--sections", default="c1,c2,c3,c4,c5,mix",
                     help="comma list of workloads to run besides the headline (c2 is always run)")
     ap.add_argument("--serving-requests", type=int, default=200)
     ap.add_argument("--no-autotune", action="store_true")
@@ -143,6 +145,33 @@ def bench_c1(V, torch, args):
         o = out.cpu().numpy()
         res[name] = {"ms": 1e3 * sec, "terms_per_s": D / sec, "samples_per_s": D * N * R / sec,
                      "logF": float(o[0]), "se": float(o[1])}
+    V.vecchia_plan_destroy(plan)
+    return res
+
+
+def bench_mixture(V, torch, args):
+    """Scale-mixture CDF G(x) = E Phi_D(x / R), R Pareto(gamma = 2) (eqs. (8)-(9)),
+    on the headline geometry: 32 Gauss-Laguerre nodes + 2 first-pass scales."""
+    import workloads as W
+    inst = W.uniform2500_matern15()
+    stream = torch.cuda.Stream()
+    sp = stream.cuda_stream
+    plan = V.vecchia_plan(inst.locs, inst.ordering, inst.m, inst.cov, stream=sp)
+    x = torch.tensor(inst.x, dtype=torch.float64, device="cuda")
+    out = torch.empty(2, dtype=torch.float64, device="cuda")
+    mix = V.make_mixture(0.0, 2.0, 32)
+    res = {"workload": inst.name + "_pareto2_mixture", "beta": 0.0, "gamma": 2.0, "n_nodes": 32,
+           "evaluations_per_call": 34}
+    got = {}
+    for name, prec, reps in (("fp32", V.VECCHIA_FP32_LOOP, 5), ("fp64", V.VECCHIA_FP64, 1)):
+        q = V.make_qmc(inst.qmc.n_points, inst.qmc.n_shifts, inst.qmc.seed, prec)
+        sec = _timed(torch, lambda: V.vecchia_mixture_logcdf(plan, x, mix, q, out, stream=sp), reps)
+        o = out.cpu().numpy()
+        got[name] = o
+        res[name] = {"ms_per_call": 1e3 * sec, "calls_per_s": 1.0 / sec,
+                     "terms_per_s": 34 * inst.D / sec, "logG": float(o[0]), "se": float(o[1])}
+    res["fp32_speedup"] = res["fp64"]["ms_per_call"] / res["fp32"]["ms_per_call"]
+    res["fp32_vs_fp64_rel"] = abs(got["fp32"][0] - got["fp64"][0]) / abs(got["fp64"][0])
     V.vecchia_plan_destroy(plan)
     return res
 
@@ -415,6 +444,8 @@ def main():
         res["c4_large"] = bench_c4(V, torch, args)
     if "c5" in sections:
         res["c5_serving"] = bench_c5(V, torch, args)
+    if "mix" in sections:
+        res["scale_mixture"] = bench_mixture(V, torch, args)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(inst, args.cpu_terms)
     print(json.dumps(res), flush=True)

@@ -89,6 +89,17 @@ typedef struct {
   int32_t reserved;   /* must be 0                                                  */
 } vecchia_qmc;
 
+/* Mixing law of the Gaussian scale mixture X = R W (Section 4, eqs. (7)-(8)):
+ * F_R(r) = 1 - exp{-gamma (r^beta - 1) / beta} for beta > 0, and the Pareto law
+ * 1 - r^-gamma for beta = 0 (eq. (8) prints 1 - r^gamma, negative for r > 1),
+ * both on r >= 1. */
+typedef struct {
+  double beta;        /* >= 0                                                   */
+  double gamma;       /* > 0                                                    */
+  int32_t n_nodes;    /* Gauss-Laguerre nodes of the outer integral, 1..64     */
+  int32_t reserved;   /* must be 0                                              */
+} vecchia_mixture;
+
 /* Message for the calling thread's last non-OK status ("" if none). */
 const char* vecchia_last_error(void);
 
@@ -191,6 +202,30 @@ vecchia_status vecchia_profile_enable(int32_t on);
 vecchia_status vecchia_profile_read(int32_t K, int32_t precision, double* total_ms, int64_t* launches,
                                     int64_t* sov_steps);
 vecchia_status vecchia_profile_reset(void);
+
+/* Scale-mixture marginal CDF, eq. (9): G(x) = int_1^inf Phi_D(x / r) f_R(r) dr,
+ * each Phi_D a Vecchia log-CDF of the plan (as vecchia_logcdf with
+ * scale = r). With v = -log(1 - F_R(R)) ~ Exp(1) the integral is
+ * int_0^inf e^-v Phi_D(x / r(v)) dv; pass 1 evaluates the plan at v = 0 and
+ * v = 1e-3 (one batched launch) to get mu = 1 + max(0, -d log Phi_D / dv), pass 2
+ * at the n Gauss-Laguerre nodes tau_k / mu (one batched launch), and a device
+ * kernel combines them in log space:
+ *   out_dev[0] = log G = log sum_k (w_k / mu) e^(tau_k (1 - 1/mu)) Phi_D(x / r(tau_k / mu)),
+ *   out_dev[1] = its standard error (first-order propagation of the node SEs).
+ * Every node uses q->seed (common random numbers). x_dev: D thresholds, user
+ * order (device). cov_override as in vecchia_logcdf. nodes_dev (may be NULL):
+ * n_nodes x {log Phi_D, se} per node (device). Synchronises hip_stream once
+ * (after pass 1); the rest is asynchronous. Errors: INVALID, NOMEM, HIP;
+ * vecchia_plan_status reports NOT_PD. */
+vecchia_status vecchia_mixture_logcdf(vecchia_plan_t plan, const double* x_dev, const vecchia_mixture* mix,
+                                      const vecchia_cov* cov_override, const vecchia_qmc* q, double* out_dev,
+                                      double* nodes_dev, void* hip_stream);
+
+/* The pass-2 rule of vecchia_mixture_logcdf for a given mu >= 1 (host only):
+ * scales_out[k] = r(tau_k / mu) (capped at 1e300) and
+ * logw_out[k] = log(w_k / mu) + tau_k (1 - 1/mu), n_nodes entries each.
+ * Errors: INVALID. */
+vecchia_status vecchia_mixture_rule(const vecchia_mixture* mix, double mu, double* scales_out, double* logw_out);
 
 /* Launch-shape autotuner (the batched launch of Section 2.2, eq. (6): terms of
  * all instances that share K run in one launch, one wave per work item of

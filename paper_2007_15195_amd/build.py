@@ -32,6 +32,7 @@ SOURCES = [
     "host_order.cpp",
     "autotune.cpp",
     "calibrate.hip",
+    "mixture.cpp",
 ]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-function",

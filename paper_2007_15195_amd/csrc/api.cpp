@@ -35,6 +35,7 @@ void free_plan_buffers(vecchia_plan_s* P) {
   hipFree(P->d_perm);
   hipFree(P->d_nbr);
   hipFree(P->d_kcnt);
+  hipFree(P->d_mix);
 }
 
 vecchia_status order_impl(const double* locs, int64_t D, int32_t ordering, const int64_t* perm_in,
@@ -260,7 +261,8 @@ vecchia_status vecchia_logcdf(vecchia_plan_t plan, const double* x_dev, double s
   std::lock_guard<std::mutex> lk(plan->mu);
   Batch* b = plan->single.get();
   if (!b || b->qmcs()[0].n_shifts != q->n_shifts || b->qmcs()[0].precision != q->precision ||
-      b->qmcs()[0].n_points != q->n_points) {
+      b->qmcs()[0].n_points != q->n_points ||
+      b->chunk_points(0) != chunk_points_for(plan->m, q->precision, q->n_points)) {
     std::unique_ptr<Batch> nb;
     vecchia_status st = Batch::create({plan}, {*q}, &nb);
     if (st != VECCHIA_OK) return st;
@@ -275,11 +277,23 @@ vecchia_status vecchia_plan_status(vecchia_plan_t plan, int64_t* bad_term) {
   if (!plan) return set_error(VECCHIA_E_INVALID, "null plan");
   if (bad_term) *bad_term = -1;
   std::lock_guard<std::mutex> lk(plan->mu);
-  if (!plan->single) return VECCHIA_OK;
-  std::vector<int64_t> bad;
-  vecchia_status st = plan->single->status(&bad);
-  if (bad_term && !bad.empty()) *bad_term = bad[0];
-  return st;
+  // the first NOT_PD report of the plan's evaluation batches (single call, then
+  // the scale-mixture passes)
+  for (Batch* b : {plan->single.get(), plan->mix1.get(), plan->mix2.get()}) {
+    if (!b) continue;
+    std::vector<int64_t> bad;
+    vecchia_status st = b->status(&bad);
+    if (st == VECCHIA_E_NOT_PD) {
+      for (int64_t v : bad)
+        if (v >= 0) {
+          if (bad_term) *bad_term = v;
+          break;
+        }
+      return st;
+    }
+    if (st != VECCHIA_OK) return st;
+  }
+  return VECCHIA_OK;
 }
 
 vecchia_status vecchia_plan_destroy(vecchia_plan_t plan) {
@@ -288,6 +302,8 @@ vecchia_status vecchia_plan_destroy(vecchia_plan_t plan) {
   if (plan->single && plan->single->last_stream() != nullptr) hipStreamSynchronize(plan->single->last_stream());
   hipDeviceSynchronize();
   plan->single.reset();
+  plan->mix1.reset();
+  plan->mix2.reset();
   free_plan_buffers(plan);
   delete plan;
   return VECCHIA_OK;

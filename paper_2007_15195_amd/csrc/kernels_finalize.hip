@@ -121,7 +121,48 @@ __global__ __launch_bounds__(kFinalizeThreads) void instance_logsum(const InstDe
   }
 }
 
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Scale-mixture combination (one wave, node k on lane k; fixed butterflies).
+__global__ __launch_bounds__(64) void mixture_combine(const double* __restrict__ node_out, MixWeights mw,
+                                                      double* __restrict__ out, double* __restrict__ nodes_out) {
+  const int lane = threadIdx.x;
+  const bool on = lane < mw.n;
+  const double lf = on ? node_out[2 * lane] : 0.0;
+  const double se = on ? node_out[2 * lane + 1] : 0.0;
+  const double c = on ? mw.logw[lane] + lf : -HUGE_VAL;
+  const double mx = wave_max(on ? c : -HUGE_VAL);
+  double logG;
+  if (mx == -HUGE_VAL) {
+    logG = -HUGE_VAL;    // every node's Phi_D underflowed to 0
+  } else {
+    const double sum = wave_sum(on ? exp(c - mx) : 0.0);
+    logG = mx + log(sum);
+  }
+  const double frac = on ? exp(c - logG) : 0.0;
+  const double var = wave_sum(on ? (frac * se) * (frac * se) : 0.0);
+  if (lane == 0) {
+    out[0] = logG;
+    out[1] = sqrt(var);
+  }
+  if (nodes_out && on) {
+    nodes_out[2 * lane] = lf;
+    nodes_out[2 * lane + 1] = se;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_mixture_combine(const double* node_out, const MixWeights& mw, double* out, double* nodes_out,
+                                  hipStream_t s) {
+  if (mw.n < 1 || mw.n > kMaxMixNodes) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(mixture_combine, dim3(1), dim3(64), 0, s, node_out, mw, out, nodes_out);
+  return hipGetLastError();
+}
 
 hipError_t launch_finalize(const InstDesc* d_insts, int n_inst, const int64_t* d_term_bases,
                            int64_t total_terms, const Aux64* aux64, const double* sums,

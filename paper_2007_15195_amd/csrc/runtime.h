@@ -53,6 +53,11 @@ class Batch {
   const int64_t* device_bad_terms() const { return d_bad_; }
   int n() const { return (int)plans_.size(); }
   const std::vector<vecchia_qmc>& qmcs() const { return qmcs_; }
+  int chunk_points(int j) const { return desc_[j].chunk_points; }
+  // Every instance reads the same thresholds (x_dev itself, D values) instead of
+  // consecutive slices of x_dev: several instances of one plan at different
+  // scales, as the scale-mixture quadrature needs.
+  void set_shared_x(bool on) { shared_x_ = on; }
   // After a completed run(): re-launches the launch with the most work `reps`
   // times on s between HIP events and returns the median duration (autotuner).
   vecchia_status time_main_launch(hipStream_t s, int reps, float* median_ms);
@@ -115,6 +120,7 @@ class Batch {
   char* ext_ws_ = nullptr;
   InstDesc* ext_stage_ = nullptr;
   bool tables_uploaded_ = false;
+  bool shared_x_ = false;
 
   hipGraphExec_t graph_exec_ = nullptr;
   hipStream_t graph_stream_ = nullptr;
@@ -139,6 +145,10 @@ struct vecchia_plan_s {
   int32_t* d_nbr = nullptr;
   int32_t* d_kcnt = nullptr;
   std::unique_ptr<vecchia::Batch> single;   // cached one-instance batch of vecchia_logcdf
+  // scale-mixture evaluation (vecchia_mixture_logcdf): the two passes' batches
+  // and a device buffer for their per-node results (2 x (2 + max nodes) doubles)
+  std::unique_ptr<vecchia::Batch> mix1, mix2;
+  double* d_mix = nullptr;
   // pinned staging for vecchia_replan: {xs, ys (D doubles), perm (D int32)} x 2
   char* h_replan[2] = {nullptr, nullptr};
   hipEvent_t replan_ev[2] = {nullptr, nullptr};

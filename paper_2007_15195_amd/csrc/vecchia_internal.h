@@ -69,6 +69,16 @@ hipError_t launch_setup(const InstDesc* d_insts, int n_inst, const int64_t* d_te
 hipError_t launch_qmc(int K, int precision, const InstDesc* d_insts, const RangeDesc* d_ranges,
                       int n_ranges, int64_t n_items, const Aux64* aux64, const Aux32* aux32,
                       const uint64_t* d_Z, double* sums, hipStream_t s);
+// Scale-mixture quadrature weights (log), passed by value to the combine kernel.
+constexpr int kMaxMixNodes = 64;
+struct MixWeights {
+  double logw[kMaxMixNodes];
+  int32_t n;
+};
+// out[0] = log sum_k exp(logw_k + logF_k), out[1] = sqrt(sum_k (c_k / G)^2 se_k^2)
+// from node_out (n x {log F_k, se_k}); nodes_out (optional) receives a copy of node_out.
+hipError_t launch_mixture_combine(const double* node_out, const MixWeights& mw, double* out, double* nodes_out,
+                                  hipStream_t s);
 hipError_t launch_finalize(const InstDesc* d_insts, int n_inst, const int64_t* d_term_bases,
                            int64_t total_terms, const Aux64* aux64, const double* sums,
                            double2* term_res, hipStream_t s);

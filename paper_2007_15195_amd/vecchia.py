@@ -32,6 +32,7 @@ EXPORTED = [
     "vecchia_batch_destroy", "vecchia_server_create", "vecchia_submit", "vecchia_poll",
     "vecchia_server_destroy", "vecchia_profile_enable", "vecchia_profile_read", "vecchia_profile_reset",
     "vecchia_autotune", "vecchia_tuning_get", "vecchia_tuning_set", "vecchia_calibrate_valu",
+    "vecchia_mixture_logcdf", "vecchia_mixture_rule",
 ]
 
 
@@ -44,6 +45,10 @@ class VecchiaError(RuntimeError):
 class vecchia_cov(ctypes.Structure):
     _fields_ = [("family", c_int32), ("reserved", c_int32), ("nu", c_double), ("sigma2", c_double),
                 ("range", c_double), ("nugget", c_double)]
+
+
+class vecchia_mixture(ctypes.Structure):
+    _fields_ = [("beta", c_double), ("gamma", c_double), ("n_nodes", c_int32), ("reserved", c_int32)]
 
 
 class vecchia_qmc(ctypes.Structure):
@@ -92,6 +97,9 @@ def lib():
         "vecchia_tuning_get": [c_int32, c_int32, POINTER(c_int32)],
         "vecchia_tuning_set": [c_int32, c_int32, c_int32],
         "vecchia_calibrate_valu": [c_void_p, c_void_p],
+        "vecchia_mixture_logcdf": [c_void_p, c_void_p, POINTER(vecchia_mixture), c_void_p, POINTER(vecchia_qmc),
+                                   c_void_p, c_void_p, c_void_p],
+        "vecchia_mixture_rule": [POINTER(vecchia_mixture), c_double, c_void_p, c_void_p],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -334,3 +342,28 @@ def vecchia_calibrate_valu(stream=None) -> dict:
     r = (c_double * 5)()
     _check(lib().vecchia_calibrate_valu(_stream_ptr(stream), ctypes.cast(r, c_void_p)))
     return dict(zip(("fma", "exp", "log", "rcp", "sqrt"), list(r)))
+
+
+def make_mixture(beta: float = 0.0, gamma: float = 2.0, n_nodes: int = 32) -> vecchia_mixture:
+    return vecchia_mixture(float(beta), float(gamma), int(n_nodes), 0)
+
+
+def vecchia_mixture_rule(mix: vecchia_mixture, mu: float):
+    """(scales, log weights) of the pass-2 rule for a given mu (host only)."""
+    n = int(mix.n_nodes)
+    sc = np.empty(max(1, n), dtype=np.float64)
+    lw = np.empty(max(1, n), dtype=np.float64)
+    _check(lib().vecchia_mixture_rule(byref(mix), float(mu), sc.ctypes.data, lw.ctypes.data))
+    return sc[:n], lw[:n]
+
+
+def vecchia_mixture_logcdf(plan: int, x, mix: vecchia_mixture, qmc, out, nodes=None, cov_override=None,
+                           stream=None) -> None:
+    D, _ = vecchia_plan_info(plan)
+    q = as_qmc(qmc)
+    c = as_cov(cov_override)
+    _check(lib().vecchia_mixture_logcdf(plan, _dev_ptr(x, D, "x"), byref(mix),
+                                        None if c is None else ctypes.addressof(c), byref(q),
+                                        _dev_ptr(out, 2, "out"),
+                                        None if nodes is None else _dev_ptr(nodes, 2 * int(mix.n_nodes), "nodes"),
+                                        _stream_ptr(stream)))

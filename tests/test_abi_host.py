@@ -124,3 +124,28 @@ def test_calibration_hook_rejects_missing_output():
     with pytest.raises(V.VecchiaError) as e:
         V._check(V.lib().vecchia_calibrate_valu(None, None))
     assert e.value.status == 1
+
+
+@pytest.mark.parametrize("beta,gamma", [(0.0, 2.0), (0.0, 0.3), (0.5, 1.0), (2.0, 0.5)])
+@pytest.mark.parametrize("n", [1, 2, 8, 32, 64])
+@pytest.mark.parametrize("mu", [1.0, 1.37, 195.0])
+def test_mixture_rule_matches_the_oracle(beta, gamma, n, mu):
+    # the library's own Gauss-Laguerre rule and scale map against the oracle's
+    # (numpy's laggauss and the inverse of eq. (8))
+    from oracle import mixture as M
+    sc, lw = V.vecchia_mixture_rule(V.make_mixture(beta, gamma, n), mu)
+    osc, olw = M.pass2(mu, n, beta, gamma)
+    np.testing.assert_allclose(sc, osc, rtol=1e-12, atol=0.0)
+    big = olw > -600.0            # weights below e^-600 do not contribute to any sum
+    np.testing.assert_allclose(lw[big], olw[big], rtol=0.0, atol=1e-9)
+
+
+def test_mixture_arguments_rejected_on_the_host():
+    assert ctypes.sizeof(V.vecchia_mixture) == 24
+    for mix in (V.make_mixture(-0.1, 2.0, 8), V.make_mixture(0.0, 0.0, 8), V.make_mixture(0.0, 2.0, 0),
+                V.make_mixture(0.0, 2.0, 65), V.make_mixture(float("nan"), 2.0, 8)):
+        with pytest.raises(V.VecchiaError) as e:
+            V.vecchia_mixture_rule(mix, 1.0)
+        assert e.value.status == 1
+    with pytest.raises(V.VecchiaError):
+        V.vecchia_mixture_rule(V.make_mixture(0.0, 2.0, 8), 0.5)      # mu < 1
