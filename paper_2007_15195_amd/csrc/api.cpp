@@ -1,6 +1,8 @@
 // C ABI entry points (include/vecchia.h): argument checks, plan construction
 // (host ordering + GPU nearest-neighbour kernel) and the evaluation calls.
+#include <algorithm>
 #include <cmath>
+#include <limits>
 #include <cstring>
 #include <new>
 #include <string>
@@ -36,6 +38,49 @@ void free_plan_buffers(vecchia_plan_s* P) {
   hipFree(P->d_nbr);
   hipFree(P->d_kcnt);
   hipFree(P->d_mix);
+  if (P->has_grid) {
+    hipFree(P->grid.cell);
+    hipFree(P->grid.start);
+    hipFree(P->grid.cursor);
+    hipFree(P->grid.gx);
+    hipFree(P->grid.gy);
+    hipFree(P->grid.gid);
+  }
+}
+
+// Grid geometry over the bounding box of the plan-order points: about two
+// points per cell, and a margin covering rounding in cell bounds.
+void grid_geometry(const double* xs, const double* ys, int64_t D, KnnGrid* g) {
+  double x0 = xs[0], x1 = xs[0], y0 = ys[0], y1 = ys[0];
+  for (int64_t i = 1; i < D; ++i) {
+    x0 = std::min(x0, xs[i]);
+    x1 = std::max(x1, xs[i]);
+    y0 = std::min(y0, ys[i]);
+    y1 = std::max(y1, ys[i]);
+  }
+  g->G = (int32_t)std::max<int64_t>(1, (int64_t)std::sqrt((double)D / 2.0));
+  g->x0 = x0;
+  g->y0 = y0;
+  g->wx = x1 > x0 ? (x1 - x0) / g->G : 1.0;
+  g->wy = y1 > y0 ? (y1 - y0) / g->G : 1.0;
+  const double mag = std::max(std::max(std::fabs(x0), std::fabs(x1)), std::max(std::fabs(y0), std::fabs(y1))) +
+                     g->G * std::max(g->wx, g->wy);
+  g->margin = 16.0 * std::numeric_limits<double>::epsilon() * mag;
+}
+
+hipError_t alloc_grid(vecchia_plan_s* P) {
+  const int64_t D = P->D;
+  KnnGrid& g = P->grid;
+  g.G = (int32_t)std::max<int64_t>(1, (int64_t)std::sqrt((double)D / 2.0));
+  const int64_t cells = (int64_t)g.G * g.G;
+  P->has_grid = true;
+  hipError_t e = dev_alloc(&g.cell, D);
+  if (e == hipSuccess) e = dev_alloc(&g.start, cells + 1);
+  if (e == hipSuccess) e = dev_alloc(&g.cursor, cells);
+  if (e == hipSuccess) e = dev_alloc(&g.gx, D);
+  if (e == hipSuccess) e = dev_alloc(&g.gy, D);
+  if (e == hipSuccess) e = dev_alloc(&g.gid, D);
+  return e;
 }
 
 vecchia_status order_impl(const double* locs, int64_t D, int32_t ordering, const int64_t* perm_in,
@@ -110,10 +155,15 @@ vecchia_status vecchia_plan(const double* locs_host, int64_t D, int32_t dim, int
   if (e == hipSuccess) e = dev_alloc(&P->d_perm, D);
   if (e == hipSuccess) e = dev_alloc(&P->d_kcnt, D);
   if (e == hipSuccess && m > 0) e = dev_alloc(&P->d_nbr, (size_t)D * m);
+  if (e == hipSuccess && m > 0 && D > kKnnGridMinD) {
+    e = alloc_grid(P);
+    grid_geometry(hx.data(), hy.data(), D, &P->grid);
+  }
   if (e == hipSuccess) e = hipMemcpyAsync(P->d_xs, hx.data(), sizeof(double) * D, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(P->d_ys, hy.data(), sizeof(double) * D, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(P->d_perm, hp.data(), sizeof(int32_t) * D, hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = launch_knn(P->d_xs, P->d_ys, D, m, P->d_nbr, P->d_kcnt, s);
+  if (e == hipSuccess)
+    e = launch_knn(P->d_xs, P->d_ys, D, m, P->d_nbr, P->d_kcnt, P->has_grid ? &P->grid : nullptr, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e == hipSuccess) {
     P->kcnt.resize(D);
@@ -228,7 +278,10 @@ vecchia_status vecchia_replan(vecchia_plan_t plan, const double* locs_host, int3
   if (e == hipSuccess) e = hipMemcpyAsync(plan->d_ys, hy, sizeof(double) * D, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(plan->d_perm, hp, sizeof(int32_t) * D, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipEventRecord(plan->replan_ev[k], s);
-  if (e == hipSuccess) e = launch_knn(plan->d_xs, plan->d_ys, D, plan->m, plan->d_nbr, plan->d_kcnt, s);
+  if (plan->has_grid) grid_geometry(hx, hy, D, &plan->grid);
+  if (e == hipSuccess)
+    e = launch_knn(plan->d_xs, plan->d_ys, D, plan->m, plan->d_nbr, plan->d_kcnt,
+                   plan->has_grid ? &plan->grid : nullptr, s);
   if (e != hipSuccess) return hip_error(e, "replan");
   plan->replan_used[k] = true;
   plan->perm = std::move(perm);   // k_i = min(m, i) is unchanged

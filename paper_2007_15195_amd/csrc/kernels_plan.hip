@@ -22,14 +22,15 @@ template <int M>
 __global__ __launch_bounds__(64 * kKnnWaves) void knn_preceding(const double* __restrict__ xs,
                                                                 const double* __restrict__ ys, int64_t D,
                                                                 int32_t* __restrict__ nbr,
-                                                                int32_t* __restrict__ kcnt, int64_t q_base) {
+                                                                int32_t* __restrict__ kcnt, int64_t q_base,
+                                                                int64_t q_end) {
 #pragma clang fp contract(off)
   __shared__ double2 tile[kKnnTile];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t q0 = q_base + (int64_t)blockIdx.x * kKnnWaves;
   const int64_t i = q0 + wave;
-  const bool valid = i < D;
+  const bool valid = i < q_end;
   const double qx = valid ? xs[i] : 0.0;
   const double qy = valid ? ys[i] : 0.0;
   double bd[M];
@@ -39,7 +40,7 @@ __global__ __launch_bounds__(64 * kKnnWaves) void knn_preceding(const double* __
     bd[s] = HUGE_VAL;
     bj[s] = -1;
   }
-  const int64_t last_query = (q0 + kKnnWaves < D ? q0 + kKnnWaves : D) - 1;
+  const int64_t last_query = (q0 + kKnnWaves < q_end ? q0 + kKnnWaves : q_end) - 1;
   for (int64_t t0 = 0; t0 < last_query; t0 += kKnnTile) {
     __syncthreads();
     for (int c = threadIdx.x; c < kKnnTile; c += 64 * kKnnWaves) {
@@ -99,6 +100,138 @@ __global__ __launch_bounds__(64 * kKnnWaves) void knn_preceding(const double* __
   if (lane == 0) kcnt[i] = k;
 }
 
+__device__ __forceinline__ int grid_cell(double v, double lo, double w, int G) {
+  const int c = (int)floor((v - lo) / w);
+  return c < 0 ? 0 : (c >= G ? G - 1 : c);
+}
+
+__global__ __launch_bounds__(256) void grid_count(const double* __restrict__ xs, const double* __restrict__ ys,
+                                                  int64_t D, KnnGrid g) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= D) return;
+  const int c = grid_cell(xs[i], g.x0, g.wx, g.G) * g.G + grid_cell(ys[i], g.y0, g.wy, g.G);
+  g.cell[i] = c;
+  atomicAdd(&g.cursor[c], 1);   // counts (the cursor array starts at zero)
+}
+
+// Exclusive scan of the G*G counts (in cursor) into start[0..G*G]; cursor then
+// holds each cell's first slot. One block of 1024 threads, each a contiguous
+// segment.
+__global__ __launch_bounds__(1024) void grid_scan(KnnGrid g) {
+  __shared__ int64_t part[1024];
+  const int64_t n = (int64_t)g.G * g.G;
+  const int64_t per = (n + 1023) / 1024;
+  const int64_t b = (int64_t)threadIdx.x * per;
+  const int64_t e = b + per < n ? b + per : n;
+  int64_t sum = 0;
+  for (int64_t c = b; c < e; ++c) sum += g.cursor[c];
+  part[threadIdx.x] = sum;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {   // inclusive Hillis-Steele scan of the partial sums
+    const int64_t v = threadIdx.x >= (unsigned)o ? part[threadIdx.x - o] : 0;
+    __syncthreads();
+    part[threadIdx.x] += v;
+    __syncthreads();
+  }
+  int64_t run = part[threadIdx.x] - sum;   // exclusive prefix of this segment
+  for (int64_t c = b; c < e; ++c) {
+    const int32_t cnt = g.cursor[c];
+    g.start[c] = (int32_t)run;
+    g.cursor[c] = (int32_t)run;
+    run += cnt;
+  }
+  if (threadIdx.x == 1023) g.start[n] = (int32_t)part[1023];
+}
+
+__global__ __launch_bounds__(256) void grid_scatter(const double* __restrict__ xs, const double* __restrict__ ys,
+                                                    int64_t D, KnnGrid g) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= D) return;
+  const int q = atomicAdd(&g.cursor[g.cell[i]], 1);
+  g.gx[q] = xs[i];
+  g.gy[q] = ys[i];
+  g.gid[q] = (int32_t)i;
+}
+
+template <int M>
+__global__ __launch_bounds__(256) void knn_grid(const double* __restrict__ xs, const double* __restrict__ ys,
+                                                int64_t D, KnnGrid g, int32_t* __restrict__ nbr,
+                                                int32_t* __restrict__ kcnt, int64_t q_base) {
+#pragma clang fp contract(off)
+  const int64_t i = q_base + (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= D) return;
+  const int k = (int)(i < M ? i : M);
+  kcnt[i] = k;
+  if (k == 0) {
+    for (int s = 0; s < M; ++s) nbr[i * M + s] = -1;
+    return;
+  }
+  const double qx = xs[i], qy = ys[i];
+  const int cx = grid_cell(qx, g.x0, g.wx, g.G), cy = grid_cell(qy, g.y0, g.wy, g.G);
+  double bd[M];
+  int bj[M];
+#pragma unroll
+  for (int s = 0; s < M; ++s) {
+    bd[s] = HUGE_VAL;
+    bj[s] = 0x7fffffff;
+  }
+  const int G = g.G;
+  for (int r = 0;; ++r) {
+    const int xl = cx - r, xh = cx + r, yl = cy - r, yh = cy + r;
+    for (int x = (xl < 0 ? 0 : xl); x <= (xh > G - 1 ? G - 1 : xh); ++x) {
+      // the ring's cells in column x: all of [yl, yh] on the edge columns, else
+      // its two ends
+      const bool edge_col = x == xl || x == xh;
+      const int y0 = edge_col ? (yl < 0 ? 0 : yl) : yl;
+      const int y1 = edge_col ? (yh > G - 1 ? G - 1 : yh) : yh;
+      const int dy_step = edge_col ? 1 : (yh > yl ? yh - yl : 1);
+      for (int y = y0; y <= y1; y += dy_step) {
+        if (y < 0 || y > G - 1) continue;
+        const int c = x * G + y;
+        const int q1 = g.start[c + 1];
+        for (int q = g.start[c]; q < q1; ++q) {
+          const int j = g.gid[q];
+          if (j >= i) continue;
+          const double dx = g.gx[q] - qx;
+          const double dy = g.gy[q] - qy;
+          const double d2 = dx * dx + dy * dy;
+          if (d2 < bd[M - 1] || (d2 == bd[M - 1] && j < bj[M - 1])) {
+#pragma unroll
+            for (int s = M - 1; s > 0; --s) {
+              const bool up = d2 < bd[s - 1] || (d2 == bd[s - 1] && j < bj[s - 1]);
+              const bool here = !up && (d2 < bd[s] || (d2 == bd[s] && j < bj[s]));
+              bd[s] = up ? bd[s - 1] : (here ? d2 : bd[s]);
+              bj[s] = up ? bj[s - 1] : (here ? j : bj[s]);
+            }
+            if (d2 < bd[0] || (d2 == bd[0] && j < bj[0])) {
+              bd[0] = d2;
+              bj[0] = j;
+            }
+          }
+        }
+      }
+    }
+    if (xl <= 0 && yl <= 0 && xh >= G - 1 && yh >= G - 1) break;   // every cell visited
+    // k-th smallest key so far (selected with static indices: a dynamic index
+    // would move the list out of registers)
+    double kth = bd[0];
+#pragma unroll
+    for (int s = 1; s < M; ++s) kth = s == k - 1 ? bd[s] : kth;
+    if (kth < HUGE_VAL) {
+      // every unvisited point is at least `edge` away from the query
+      double edge = HUGE_VAL;
+      if (xl > 0) edge = fmin(edge, qx - (g.x0 + xl * g.wx));
+      if (xh < G - 1) edge = fmin(edge, (g.x0 + (xh + 1) * g.wx) - qx);
+      if (yl > 0) edge = fmin(edge, qy - (g.y0 + yl * g.wy));
+      if (yh < G - 1) edge = fmin(edge, (g.y0 + (yh + 1) * g.wy) - qy);
+      edge -= g.margin;
+      if (edge > 0.0 && kth < edge * edge) break;
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < M; ++s) nbr[i * M + s] = s < k ? bj[s] : -1;
+}
+
 __global__ void fill_i64(int64_t* p, int64_t n, int64_t v) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -111,12 +244,26 @@ __global__ void fill_i32(int32_t* p, int64_t n, int32_t v) {
 
 template <int M>
 hipError_t knn_dispatch(const double* xs, const double* ys, int64_t D, int32_t* nbr, int32_t* kcnt,
-                        hipStream_t s) {
-  constexpr int64_t kPer = kMaxLaunchThreads / 64;   // queries (one wave each) per launch
-  for (int64_t b = 0; b < D; b += kPer) {
-    const int64_t n = D - b < kPer ? D - b : kPer;
+                        const KnnGrid* grid, hipStream_t s) {
+  // queries below q_split scan their i preceding points with a wave each; the
+  // rest (large plans only) search the grid, where preceding points are dense
+  const int64_t q_split = grid ? (D < kKnnGridMinD ? D : kKnnGridMinD) : D;
+  if (grid) {
+    constexpr int64_t kPer = kMaxLaunchThreads;   // queries (one thread each) per launch
+    for (int64_t b = q_split; b < D; b += kPer) {
+      const int64_t n = D - b < kPer ? D - b : kPer;
+      hipLaunchKernelGGL(knn_grid<M>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, xs, ys, D, *grid, nbr,
+                         kcnt, b);
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+  }
+  constexpr int64_t kPerWave = kMaxLaunchThreads / 64;   // queries (one wave each) per launch
+  for (int64_t b = 0; b < q_split; b += kPerWave) {
+    const int64_t n = q_split - b < kPerWave ? q_split - b : kPerWave;
     const unsigned blocks = (unsigned)((n + kKnnWaves - 1) / kKnnWaves);
-    hipLaunchKernelGGL(knn_preceding<M>, dim3(blocks), dim3(64 * kKnnWaves), 0, s, xs, ys, D, nbr, kcnt, b);
+    hipLaunchKernelGGL(knn_preceding<M>, dim3(blocks), dim3(64 * kKnnWaves), 0, s, xs, ys, D, nbr, kcnt, b,
+                       q_split);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -125,10 +272,30 @@ hipError_t knn_dispatch(const double* xs, const double* ys, int64_t D, int32_t* 
 
 template <int... Ms>
 hipError_t knn_switch(int m, const double* xs, const double* ys, int64_t D, int32_t* nbr,
-                      int32_t* kcnt, hipStream_t s, std::integer_sequence<int, Ms...>) {
+                      int32_t* kcnt, const KnnGrid* grid, hipStream_t s, std::integer_sequence<int, Ms...>) {
   hipError_t err = hipErrorInvalidValue;
-  ((m == Ms + 1 ? (err = knn_dispatch<Ms + 1>(xs, ys, D, nbr, kcnt, s), 0) : 0), ...);
+  ((m == Ms + 1 ? (err = knn_dispatch<Ms + 1>(xs, ys, D, nbr, kcnt, grid, s), 0) : 0), ...);
   return err;
+}
+
+hipError_t build_grid(const double* xs, const double* ys, int64_t D, const KnnGrid& g, hipStream_t s) {
+  const int64_t cells = (int64_t)g.G * g.G;
+  hipLaunchKernelGGL(fill_i32, dim3((unsigned)((cells + 255) / 256)), dim3(256), 0, s, g.cursor, cells, 0);
+  hipError_t e = hipGetLastError();
+  const unsigned blocks = (unsigned)((D + 255) / 256);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(grid_count, dim3(blocks), dim3(256), 0, s, xs, ys, D, g);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(grid_scan, dim3(1), dim3(1024), 0, s, g);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(grid_scatter, dim3(blocks), dim3(256), 0, s, xs, ys, D, g);
+    e = hipGetLastError();
+  }
+  return e;
 }
 
 }  // namespace
@@ -140,14 +307,19 @@ hipError_t launch_fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t s) {
 }
 
 hipError_t launch_knn(const double* xs, const double* ys, int64_t D, int m, int32_t* nbr,
-                      int32_t* kcnt, hipStream_t s) {
+                      int32_t* kcnt, const KnnGrid* grid, hipStream_t s) {
   if (D <= 0) return hipSuccess;
   if (m == 0) {
     hipLaunchKernelGGL(fill_i32, dim3((unsigned)((D + 255) / 256)), dim3(256), 0, s, kcnt, D, 0);
     return hipGetLastError();
   }
   if (m < 1 || m > kMaxM) return hipErrorInvalidValue;
-  return knn_switch(m, xs, ys, D, nbr, kcnt, s, std::make_integer_sequence<int, kMaxM>{});
+  if (grid) {
+    if (D > 0x7fffffffLL || (int64_t)grid->G * grid->G + 1 > 0x7fffffffLL) return hipErrorInvalidValue;
+    const hipError_t e = build_grid(xs, ys, D, *grid, s);
+    if (e != hipSuccess) return e;
+  }
+  return knn_switch(m, xs, ys, D, nbr, kcnt, grid, s, std::make_integer_sequence<int, kMaxM>{});
 }
 
 }  // namespace vecchia

@@ -144,6 +144,9 @@ struct vecchia_plan_s {
   int32_t* d_perm = nullptr;
   int32_t* d_nbr = nullptr;
   int32_t* d_kcnt = nullptr;
+  // neighbour-search grid of large plans (kKnnGridMinD); geometry refreshed by replan
+  bool has_grid = false;
+  vecchia::KnnGrid grid{};
   std::unique_ptr<vecchia::Batch> single;   // cached one-instance batch of vecchia_logcdf
   // scale-mixture evaluation (vecchia_mixture_logcdf): the two passes' batches
   // and a device buffer for their per-node results (2 x (2 + max nodes) doubles)

@@ -60,9 +60,25 @@ struct Aux64 { double e0; double lt0; };   // Phi(b_0/L_00) and its log
 // ec0 = 1 - e0, neg0 = 1 if b_0/L_00 <= 0.
 struct Aux32 { float em0, en0, ec0, neg0; };
 
+// Uniform grid over the bounding box for the nearest-neighbour search of large
+// plans: G x G cells, points of cell c at [start[c], start[c+1]) of gx/gy/gid.
+struct KnnGrid {
+  int32_t G;
+  double x0, y0, wx, wy;
+  double margin;        // absolute slack for rounding in cell bounds
+  int32_t* cell;        // D: cell of each plan point
+  int32_t* start;       // G*G + 1
+  int32_t* cursor;      // G*G (scatter positions)
+  double* gx;           // D, points in cell order
+  double* gy;
+  int32_t* gid;         // D: plan index of each slot
+};
+// Plans with more points than this search neighbours through the grid.
+constexpr int64_t kKnnGridMinD = 16384;
+
 // Launchers (kernels_*.hip).
 hipError_t launch_knn(const double* xs, const double* ys, int64_t D, int m, int32_t* nbr,
-                      int32_t* kcnt, hipStream_t s);
+                      int32_t* kcnt, const KnnGrid* grid, hipStream_t s);
 hipError_t launch_fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t s);
 hipError_t launch_setup(const InstDesc* d_insts, int n_inst, const int64_t* d_term_bases,
                         int64_t total_terms, Aux64* aux64, Aux32* aux32, hipStream_t s);

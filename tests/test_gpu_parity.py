@@ -60,6 +60,45 @@ def test_neighbours_and_order_match_oracle(case):
         assert np.all(nbr[i, len(row):] == -1)
 
 
+@pytest.mark.parametrize("case", ["uniform40k_maxmin_m10", "lattice_coord_m8", "repeated_given_m15",
+                                  "thin_strip_coord_m20", "uniform20k_maxmin_m31"])
+def test_grid_neighbour_search_matches_oracle(case):
+    # plans above the grid threshold (16,384 points) search through the cell grid;
+    # sampled rows (every k < m row, the last row and random rows) must equal the
+    # brute-force definition bit for bit, ties included
+    torch_cuda()
+    from paper_2007_15195_amd import vecchia as V
+    from oracle import neighbours as oracle_neighbours
+    rng = np.random.default_rng(sum(map(ord, case)))
+    given = None
+    if case == "uniform40k_maxmin_m10":
+        locs, order, m = rng.random((40_000, 2)), W.ORDER_MAXMIN, 10
+    elif case == "lattice_coord_m8":          # 200 x 150 lattice: many equal distances
+        locs = np.array([(a / 199.0, b / 149.0) for a in range(200) for b in range(150)])
+        order, m = W.ORDER_COORD, 8
+    elif case == "repeated_given_m15":        # every location twice, random order
+        base = rng.random((10_000, 2))
+        locs = np.repeat(base, 2, axis=0)
+        order, m, given = W.ORDER_GIVEN, 15, rng.permutation(20_000)
+    elif case == "thin_strip_coord_m20":      # a strip far from the origin
+        locs = rng.random((20_000, 2)) * np.array([1e-6, 1.0]) + 1e3
+        order, m = W.ORDER_COORD, 20
+    else:
+        locs, order, m = rng.random((20_000, 2)), W.ORDER_MAXMIN, 31
+    D = locs.shape[0]
+    cov = V.make_cov(V.VECCHIA_COV_MATERN, 1.5, 1.0, 0.1, 1e-8)
+    plan = V.vecchia_plan(locs, order, m, cov, perm=given)
+    perm, nbr = V.vecchia_plan_neighbours(plan)
+    V.vecchia_plan_destroy(plan)
+    s = locs[perm]
+    q = np.unique(np.concatenate([np.arange(0, 2 * m + 2), rng.choice(D, 400, replace=False), [D - 1]]))
+    ref = oracle_neighbours.knn_preceding(s, m, queries=q)
+    for i, r in zip(q, ref):
+        row = nbr[i][nbr[i] >= 0]
+        assert np.array_equal(row, r), (case, int(i))
+        assert np.all(nbr[i, len(row):] == -1)
+
+
 # ------------------------------------------------------------- FP64 mode ---
 
 def test_fp64_grid400_full_parity():
