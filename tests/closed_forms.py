@@ -58,3 +58,27 @@ def monte_carlo_cdf(Sigma, b, n: int, seed: int, batch: int = 1_000_000):
         done += nb
     p = hits / n
     return p, math.sqrt(p * (1.0 - p) / n)
+
+
+def bivariate_owen(h: float, k: float, rho: float) -> float:
+    """P(X1 < h, X2 < k), unit variances, correlation rho, by Owen's (1956)
+    T-function identity (h, k != 0):
+      1/2 [Phi(h) + Phi(k)] - T(h, a_h) - T(k, a_k) - delta,
+      a_h = (k - rho h) / (h sqrt(1 - rho^2)), a_k = (h - rho k) / (k sqrt(1 - rho^2)),
+      delta = 0 if h k > 0 else 1/2."""
+    from scipy.special import owens_t
+    s = math.sqrt(1.0 - rho * rho)
+    ah = (k - rho * h) / (h * s)
+    ak = (h - rho * k) / (k * s)
+    delta = 0.0 if h * k > 0.0 else 0.5
+    return 0.5 * (float(ndtr(h)) + float(ndtr(k))) - float(owens_t(h, ah)) - float(owens_t(k, ak)) - delta
+
+
+def one_factor_cdf(y, a: float, c: float) -> float:
+    """P(Y < y) for Y_j = sqrt(a) Z + sqrt(c) E_j (Z, E_j iid N(0, 1)), i.e.
+    covariance c I + a 1 1^T: int phi(z) prod_j Phi((y_j - sqrt(a) z) / sqrt(c)) dz."""
+    y = np.asarray(y, dtype=np.float64)
+    sa, sc = math.sqrt(a), math.sqrt(c)
+    f = lambda z: norm.pdf(z) * float(np.prod(ndtr((y - sa * z) / sc)))
+    val, _ = integrate.quad(f, -np.inf, np.inf, epsabs=1e-15, epsrel=1e-12, limit=400)
+    return val
