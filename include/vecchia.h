@@ -71,6 +71,7 @@ enum { VECCHIA_FP64 = 0, VECCHIA_FP32_LOOP = 1 };
 #define VECCHIA_MAX_M 31          /* conditioning-set size limit (term dimension <= 32) */
 #define VECCHIA_MAX_SHIFTS 65536
 #define VECCHIA_MAX_POINTS 1073741824
+#define VECCHIA_MIX_SEARCH_NODES 24   /* search points of the scale-mixture rule */
 
 typedef struct {
   int32_t family;   /* VECCHIA_COV_*                                  */
@@ -96,7 +97,7 @@ typedef struct {
 typedef struct {
   double beta;        /* >= 0                                                   */
   double gamma;       /* > 0                                                    */
-  int32_t n_nodes;    /* Gauss-Laguerre nodes of the outer integral, 1..64     */
+  int32_t n_nodes;    /* Gauss-Legendre nodes of the outer integral, 1..64     */
   int32_t reserved;   /* must be 0                                              */
 } vecchia_mixture;
 
@@ -132,12 +133,42 @@ vecchia_status vecchia_plan(const double* locs_host, int64_t D, int32_t dim, int
 vecchia_status vecchia_plan_from_cov(const double* cov_host, int64_t D, const int32_t* nbr_host,
                                      int32_t m, void* hip_stream, vecchia_plan_t* out);
 
+/* Censored plan of one replicate (Section 4, eq. (11)). observed_host: D flags
+ * in user order, 1 = the site's value is observed (above the censoring
+ * threshold: the likelihood takes the density there), 0 = censored (only
+ * X_i <= x_i is known, x_i being the threshold). The sites are ordered by
+ * `ordering` (as vecchia_plan), then every observed site is moved before every
+ * censored one, each group keeping its relative order; neighbours are the m
+ * nearest preceding sites in that order. vecchia_logcdf on this plan at scale r
+ * returns the Vecchia form of eq. (11)'s integrand,
+ *   log L_r(x) = sum_{i observed} log f(x_i / r | x_{N_i} / r) - |I| log r
+ *              + sum_{i censored} log P(X_i <= x_i / r | censored neighbours <= x / r,
+ *                                            observed neighbours = x / r),
+ * each censored term an SOV/QMC ratio of the conditional Gaussian given its
+ * observed neighbours (dimension: its censored neighbours + 1); the per-term
+ * output holds the density terms with SE 0. vecchia_mixture_logcdf on it
+ * returns log G_I(x). With no observed site the plan equals vecchia_plan's.
+ * Errors: as vecchia_plan, and INVALID for flags other than 0 / 1. */
+vecchia_status vecchia_plan_censored(const double* locs_host, int64_t D, int32_t dim, int32_t ordering,
+                                     const int64_t* perm_in_host, const uint8_t* observed_host, int32_t m,
+                                     const vecchia_cov* cov, void* hip_stream, vecchia_plan_t* out);
+
+/* Censored plan over an explicit covariance (as vecchia_plan_from_cov) whose
+ * first n_observed variables are the observed ones (0 <= n_observed <= D).
+ * Errors: as vecchia_plan_from_cov, and INVALID for n_observed outside 0..D. */
+vecchia_status vecchia_plan_from_cov_censored(const double* cov_host, int64_t D, const int32_t* nbr_host,
+                                              int32_t m, int64_t n_observed, void* hip_stream,
+                                              vecchia_plan_t* out);
+
+/* Number of observed sites of a plan (plan positions 0..n-1; 0 for a plain plan). */
+vecchia_status vecchia_plan_censoring(vecchia_plan_t plan, int64_t* n_observed);
+
 /* Recompute a geometry plan in place for new locations (same D, m and
  * covariance family): host ordering, then an asynchronous copy and the
  * knn_preceding kernel on hip_stream. Allocates nothing; the host ordering of
  * this call overlaps GPU work already queued. Must be ordered with the plan's
  * other calls on one stream. locs_host / perm_in_host as in vecchia_plan.
- * Errors: INVALID (matrix plan, bad arguments), HIP. */
+ * Errors: INVALID (matrix or censored plan, bad arguments), HIP. */
 vecchia_status vecchia_replan(vecchia_plan_t plan, const double* locs_host, int32_t ordering,
                               const int64_t* perm_in_host, void* hip_stream);
 
@@ -203,29 +234,42 @@ vecchia_status vecchia_profile_read(int32_t K, int32_t precision, double* total_
                                     int64_t* sov_steps);
 vecchia_status vecchia_profile_reset(void);
 
-/* Scale-mixture marginal CDF, eq. (9): G(x) = int_1^inf Phi_D(x / r) f_R(r) dr,
- * each Phi_D a Vecchia log-CDF of the plan (as vecchia_logcdf with
- * scale = r). With v = -log(1 - F_R(R)) ~ Exp(1) the integral is
- * int_0^inf e^-v Phi_D(x / r(v)) dv; pass 1 evaluates the plan at v = 0 and
- * v = 1e-3 (one batched launch) to get mu = 1 + max(0, -d log Phi_D / dv), pass 2
- * at the n Gauss-Laguerre nodes tau_k / mu (one batched launch), and a device
- * kernel combines them in log space:
- *   out_dev[0] = log G = log sum_k (w_k / mu) e^(tau_k (1 - 1/mu)) Phi_D(x / r(tau_k / mu)),
+/* Scale-mixture marginal CDF, eq. (9): G(x) = int_1^inf h(r) f_R(r) dr with
+ * h(r) the plan's vecchia_logcdf value at scale r: Phi_D(x / r) for a plain plan,
+ * and for a censored plan (vecchia_plan_censored) the integrand of eq. (11), so
+ * that G is the censored likelihood G_I(x). With v = -log(1 - F_R(R)) ~ Exp(1)
+ * the integral is int_0^inf e^-v h(r(v)) dv, r(v) = e^(v / gamma) (beta = 0) or
+ * (1 + beta v / gamma)^(1 / beta), capped at 1e300. Two batched passes:
+ *   1. search: log h at v = 0 and v_j = 1e-4 (2e6)^((j-1)/22), j = 1..23, with
+ *      max(64, 64 ceil(n_points / 1024)) lattice points (q's shifts and seed);
+ *   2. the window [lo, hi] of vecchia_mixture_rule and n_nodes-point
+ *      Gauss-Legendre on it at q's full size, combined on the device:
+ *   out_dev[0] = log G = log sum_k w_k e^(-v_k) h(r(v_k)),
  *   out_dev[1] = its standard error (first-order propagation of the node SEs).
  * Every node uses q->seed (common random numbers). x_dev: D thresholds, user
  * order (device). cov_override as in vecchia_logcdf. nodes_dev (may be NULL):
- * n_nodes x {log Phi_D, se} per node (device). Synchronises hip_stream once
- * (after pass 1); the rest is asynchronous. Errors: INVALID, NOMEM, HIP;
- * vecchia_plan_status reports NOT_PD. */
+ * n_nodes x {log h, se} per node (device). Synchronises hip_stream once
+ * (after pass 1); the rest is asynchronous. The window holds the mode of
+ * log h(v) - v that contains the search maximum (all of the mass for a unimodal
+ * integrand). Errors: INVALID, NOMEM, HIP; NOT_PD through vecchia_plan_status. */
 vecchia_status vecchia_mixture_logcdf(vecchia_plan_t plan, const double* x_dev, const vecchia_mixture* mix,
                                       const vecchia_cov* cov_override, const vecchia_qmc* q, double* out_dev,
                                       double* nodes_dev, void* hip_stream);
 
-/* The pass-2 rule of vecchia_mixture_logcdf for a given mu >= 1 (host only):
- * scales_out[k] = r(tau_k / mu) (capped at 1e300) and
- * logw_out[k] = log(w_k / mu) + tau_k (1 - 1/mu), n_nodes entries each.
- * Errors: INVALID. */
-vecchia_status vecchia_mixture_rule(const vecchia_mixture* mix, double mu, double* scales_out, double* logw_out);
+/* The search scales r(v_j) of vecchia_mixture_logcdf's first pass (host only):
+ * VECCHIA_MIX_SEARCH_NODES values. Errors: INVALID. */
+vecchia_status vecchia_mixture_search(const vecchia_mixture* mix, double* scales_out);
+
+/* The second-pass rule of vecchia_mixture_logcdf for given search values
+ * (host only). search_logh: VECCHIA_MIX_SEARCH_NODES values log h(v_j). With
+ * l_j = search_logh[j] - v_j and j* its (first) maximum, window_out = {lo, hi}:
+ * lo = the v_j nearest below j* with l_j < l_j* - 36 (else 0), hi = the one
+ * nearest above (else 200). Then n_nodes Gauss-Legendre points on [lo, hi], in
+ * s = log v when lo > 0 and hi / lo > 8, else in v: v_out[k], scales_out[k] =
+ * r(v_k) and logw_out[k] = log(w_k times the map's Jacobian) - v_k.
+ * Errors: INVALID (bad mixture, a NaN search value). */
+vecchia_status vecchia_mixture_rule(const vecchia_mixture* mix, const double* search_logh, double* window_out,
+                                    double* v_out, double* scales_out, double* logw_out);
 
 /* Launch-shape autotuner (the batched launch of Section 2.2, eq. (6): terms of
  * all instances that share K run in one launch, one wave per work item of

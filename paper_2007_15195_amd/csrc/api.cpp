@@ -37,6 +37,7 @@ void free_plan_buffers(vecchia_plan_s* P) {
   hipFree(P->d_perm);
   hipFree(P->d_nbr);
   hipFree(P->d_kcnt);
+  hipFree(P->d_sovk);
   hipFree(P->d_mix);
   if (P->has_grid) {
     hipFree(P->grid.cell);
@@ -83,6 +84,18 @@ hipError_t alloc_grid(vecchia_plan_s* P) {
   return e;
 }
 
+// SOV dimension of each term of a censored plan: 0 for an uncensored site (its
+// term is a conditional density), else the number of censored neighbours (the
+// uncensored ones are conditioned on by equality and add no dimension).
+void set_sov_dims(vecchia_plan_s* P, const std::vector<int32_t>& nbr) {
+  P->sovk.assign(P->D, 0);
+  for (int64_t i = P->n_obs; i < P->D; ++i) {
+    int c = 0;
+    for (int a = 0; a < P->kcnt[i]; ++a) c += nbr[(size_t)i * P->m + a] >= P->n_obs;
+    P->sovk[i] = c;
+  }
+}
+
 vecchia_status order_impl(const double* locs, int64_t D, int32_t ordering, const int64_t* perm_in,
                           int64_t* perm_out) {
   if (!locs || !perm_out) return set_error(VECCHIA_E_INVALID, "null pointer");
@@ -123,37 +136,37 @@ vecchia_status vecchia_order(const double* locs_host, int64_t D, int32_t orderin
   return order_impl(locs_host, D, ordering, perm_in_host, perm_out_host);
 }
 
-vecchia_status vecchia_plan(const double* locs_host, int64_t D, int32_t dim, int32_t ordering,
-                            const int64_t* perm_in_host, int32_t m, const vecchia_cov* cov,
-                            void* hip_stream, vecchia_plan_t* out) {
-  if (!out || !cov) return set_error(VECCHIA_E_INVALID, "null pointer");
-  *out = nullptr;
-  if (dim != 2) return set_error(VECCHIA_E_INVALID, "only 2-D locations are supported (dim must be 2)");
-  if (m < 0 || m > VECCHIA_MAX_M) return set_error(VECCHIA_E_INVALID, "m must be in 0..31");
-  std::string why;
-  if (!valid_cov(*cov, &why)) return set_error(VECCHIA_E_INVALID, why);
-  std::vector<int64_t> perm(D > 0 && D <= 0x7fffffffLL ? D : 0);
-  vecchia_status st = order_impl(locs_host, D, ordering, perm_in_host, perm.data());
-  if (st != VECCHIA_OK) return st;
+}  // extern "C"
+
+namespace {
+
+// Geometry plan for the plan-order permutation perm (D entries) whose first
+// n_obs positions are uncensored sites (0 for a plain plan): copies the
+// locations, finds the neighbours on the device and records the host copies of
+// k_i and of the SOV dimension of each term.
+vecchia_status build_geometry_plan(const double* locs_host, int64_t D, std::vector<int64_t> perm, int64_t n_obs,
+                                   int32_t m, const vecchia_cov* cov, void* hip_stream, vecchia_plan_t* out) {
   auto* P = new (std::nothrow) vecchia_plan_s();
   if (!P) return set_error(VECCHIA_E_NOMEM, "host allocation");
   hipGetDevice(&P->device);
   P->D = D;
   P->m = m;
   P->cov = *cov;
-  P->perm = perm;
+  P->perm = std::move(perm);
+  P->n_obs = n_obs;
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   std::vector<double> hx(D), hy(D);
   std::vector<int32_t> hp(D);
   for (int64_t i = 0; i < D; ++i) {
-    hx[i] = locs_host[2 * perm[i]];
-    hy[i] = locs_host[2 * perm[i] + 1];
-    hp[i] = (int32_t)perm[i];
+    hx[i] = locs_host[2 * P->perm[i]];
+    hy[i] = locs_host[2 * P->perm[i] + 1];
+    hp[i] = (int32_t)P->perm[i];
   }
   hipError_t e = dev_alloc(&P->d_xs, D);
   if (e == hipSuccess) e = dev_alloc(&P->d_ys, D);
   if (e == hipSuccess) e = dev_alloc(&P->d_perm, D);
   if (e == hipSuccess) e = dev_alloc(&P->d_kcnt, D);
+  if (e == hipSuccess && n_obs > 0) e = dev_alloc(&P->d_sovk, D);
   if (e == hipSuccess && m > 0) e = dev_alloc(&P->d_nbr, (size_t)D * m);
   if (e == hipSuccess && m > 0 && D > kKnnGridMinD) {
     e = alloc_grid(P);
@@ -169,6 +182,14 @@ vecchia_status vecchia_plan(const double* locs_host, int64_t D, int32_t dim, int
     P->kcnt.resize(D);
     e = hipMemcpy(P->kcnt.data(), P->d_kcnt, sizeof(int32_t) * D, hipMemcpyDeviceToHost);
   }
+  if (e == hipSuccess && n_obs > 0) {
+    std::vector<int32_t> nbr((size_t)D * m);
+    if (m > 0) e = hipMemcpy(nbr.data(), P->d_nbr, sizeof(int32_t) * D * m, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) {
+      set_sov_dims(P, nbr);
+      e = hipMemcpy(P->d_sovk, P->sovk.data(), sizeof(int32_t) * D, hipMemcpyHostToDevice);
+    }
+  }
   for (int k = 0; k < 2 && e == hipSuccess; ++k) {
     e = hipHostMalloc(reinterpret_cast<void**>(&P->h_replan[k]), (2 * sizeof(double) + sizeof(int32_t)) * D,
                       hipHostMallocDefault);
@@ -183,11 +204,58 @@ vecchia_status vecchia_plan(const double* locs_host, int64_t D, int32_t dim, int
   return VECCHIA_OK;
 }
 
-vecchia_status vecchia_plan_from_cov(const double* cov_host, int64_t D, const int32_t* nbr_host,
-                                     int32_t m, void* hip_stream, vecchia_plan_t* out) {
+vecchia_status check_plan_args(int32_t dim, int32_t m, const vecchia_cov* cov, vecchia_plan_t* out) {
+  if (!out || !cov) return set_error(VECCHIA_E_INVALID, "null pointer");
+  *out = nullptr;
+  if (dim != 2) return set_error(VECCHIA_E_INVALID, "only 2-D locations are supported (dim must be 2)");
+  if (m < 0 || m > VECCHIA_MAX_M) return set_error(VECCHIA_E_INVALID, "m must be in 0..31");
+  std::string why;
+  if (!valid_cov(*cov, &why)) return set_error(VECCHIA_E_INVALID, why);
+  return VECCHIA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+vecchia_status vecchia_plan(const double* locs_host, int64_t D, int32_t dim, int32_t ordering,
+                            const int64_t* perm_in_host, int32_t m, const vecchia_cov* cov,
+                            void* hip_stream, vecchia_plan_t* out) {
+  vecchia_status st = check_plan_args(dim, m, cov, out);
+  if (st != VECCHIA_OK) return st;
+  std::vector<int64_t> perm(D > 0 && D <= 0x7fffffffLL ? D : 0);
+  st = order_impl(locs_host, D, ordering, perm_in_host, perm.data());
+  if (st != VECCHIA_OK) return st;
+  return build_geometry_plan(locs_host, D, std::move(perm), 0, m, cov, hip_stream, out);
+}
+
+vecchia_status vecchia_plan_censored(const double* locs_host, int64_t D, int32_t dim, int32_t ordering,
+                                     const int64_t* perm_in_host, const uint8_t* observed_host, int32_t m,
+                                     const vecchia_cov* cov, void* hip_stream, vecchia_plan_t* out) {
+  vecchia_status st = check_plan_args(dim, m, cov, out);
+  if (st != VECCHIA_OK) return st;
+  if (!observed_host) return set_error(VECCHIA_E_INVALID, "null pointer");
+  std::vector<int64_t> base(D > 0 && D <= 0x7fffffffLL ? D : 0);
+  st = order_impl(locs_host, D, ordering, perm_in_host, base.data());
+  if (st != VECCHIA_OK) return st;
+  for (int64_t u = 0; u < D; ++u)
+    if (observed_host[u] > 1) return set_error(VECCHIA_E_INVALID, "observed flags must be 0 or 1");
+  std::vector<int64_t> perm;
+  perm.reserve(D);
+  for (int64_t i = 0; i < D; ++i)
+    if (observed_host[base[i]]) perm.push_back(base[i]);
+  const int64_t n_obs = (int64_t)perm.size();
+  for (int64_t i = 0; i < D; ++i)
+    if (!observed_host[base[i]]) perm.push_back(base[i]);
+  return build_geometry_plan(locs_host, D, std::move(perm), n_obs, m, cov, hip_stream, out);
+}
+
+static vecchia_status plan_from_cov_impl(const double* cov_host, int64_t D, const int32_t* nbr_host, int32_t m,
+                                         int64_t n_obs, void* hip_stream, vecchia_plan_t* out) {
   if (!out || !cov_host) return set_error(VECCHIA_E_INVALID, "null pointer");
   *out = nullptr;
   if (D < 1 || D > 4096) return set_error(VECCHIA_E_INVALID, "D must be in 1..4096");
+  if (n_obs < 0 || n_obs > D) return set_error(VECCHIA_E_INVALID, "n_observed must be in 0..D");
   if (m < 0 || m > VECCHIA_MAX_M) return set_error(VECCHIA_E_INVALID, "m must be in 0..31");
   for (int64_t a = 0; a < D; ++a)
     for (int64_t b = 0; b < D; ++b) {
@@ -222,9 +290,11 @@ vecchia_status vecchia_plan_from_cov(const double* cov_host, int64_t D, const in
   P->D = D;
   P->m = m;
   P->matrix = true;
+  P->n_obs = n_obs;
   P->cov = vecchia_cov{VECCHIA_COV_EXPONENTIAL, 0, 0.5, 1.0, 1.0, 0.0};
   P->perm.resize(D);
   P->kcnt = kc;
+  if (n_obs > 0) set_sov_dims(P, nbr);   // reads kcnt
   std::vector<int32_t> hp(D);
   for (int64_t i = 0; i < D; ++i) {
     P->perm[i] = i;
@@ -235,6 +305,9 @@ vecchia_status vecchia_plan_from_cov(const double* cov_host, int64_t D, const in
   if (e == hipSuccess) e = dev_alloc(&P->d_perm, D);
   if (e == hipSuccess) e = dev_alloc(&P->d_kcnt, D);
   if (e == hipSuccess && m > 0) e = dev_alloc(&P->d_nbr, (size_t)D * m);
+  if (e == hipSuccess && n_obs > 0) e = dev_alloc(&P->d_sovk, D);
+  if (e == hipSuccess && n_obs > 0)
+    e = hipMemcpyAsync(P->d_sovk, P->sovk.data(), sizeof(int32_t) * D, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(P->d_cov, cov_host, sizeof(double) * D * D, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(P->d_perm, hp.data(), sizeof(int32_t) * D, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(P->d_kcnt, kc.data(), sizeof(int32_t) * D, hipMemcpyHostToDevice, s);
@@ -250,10 +323,29 @@ vecchia_status vecchia_plan_from_cov(const double* cov_host, int64_t D, const in
   return VECCHIA_OK;
 }
 
+vecchia_status vecchia_plan_from_cov(const double* cov_host, int64_t D, const int32_t* nbr_host,
+                                     int32_t m, void* hip_stream, vecchia_plan_t* out) {
+  return plan_from_cov_impl(cov_host, D, nbr_host, m, 0, hip_stream, out);
+}
+
+vecchia_status vecchia_plan_from_cov_censored(const double* cov_host, int64_t D, const int32_t* nbr_host,
+                                              int32_t m, int64_t n_observed, void* hip_stream,
+                                              vecchia_plan_t* out) {
+  return plan_from_cov_impl(cov_host, D, nbr_host, m, n_observed, hip_stream, out);
+}
+
+vecchia_status vecchia_plan_censoring(vecchia_plan_t plan, int64_t* n_observed) {
+  if (!plan || !n_observed) return set_error(VECCHIA_E_INVALID, "null pointer");
+  *n_observed = plan->n_obs;
+  return VECCHIA_OK;
+}
+
 vecchia_status vecchia_replan(vecchia_plan_t plan, const double* locs_host, int32_t ordering,
                               const int64_t* perm_in_host, void* hip_stream) {
   if (!plan) return set_error(VECCHIA_E_INVALID, "null plan");
   if (plan->matrix) return set_error(VECCHIA_E_INVALID, "a matrix plan has no locations to re-plan");
+  if (plan->n_obs > 0)
+    return set_error(VECCHIA_E_INVALID, "a censored plan belongs to one replicate; build a new one");
   std::lock_guard<std::mutex> lk(plan->mu);
   if (plan->inflight.load() > 0) return set_error(VECCHIA_E_BUSY, "plan has requests in flight");
   const int64_t D = plan->D;

@@ -1,7 +1,9 @@
 // Steps a6-a7 (Section 2.2, eq. (6); Section 3.1) in two kernels.
 //
-// term_finalize: one wave per term (all instances of a launch). k = 0 gives
-// the exact log Phi(b_0/L_00) with SE 0; otherwise the wave's lanes take the
+// term_finalize: one wave per term (all instances of a launch). A term with no
+// SOV dimension (k = 0; in a censored plan also a density term or a censored
+// term whose neighbours are all uncensored) takes the exact value term_setup
+// wrote, with SE 0; otherwise the wave's lanes take the
 // shifts (lane r sums shift r's chunks in order), fixed butterflies give the
 // totals, and
 //     log-term = log(sum_r num_r) - log(sum_r den_r)
@@ -47,7 +49,7 @@ __global__ __launch_bounds__(64 * kFinalizeWaves) void term_finalize(
   const int64_t i = t - term_bases[ii];
   const int R = I.n_shifts;
   double lt, se2;
-  if (I.kcnt[i] == 0) {
+  if (I.sovk[i] == 0) {
     lt = aux64[t].lt0;
     se2 = 0.0;
   } else {

@@ -5,9 +5,21 @@
 // locations and thresholds b = x / scale, builds the covariance block C in LDS
 // (FP64), factors C = L L^T in place (left-looking, one lane per row) and writes
 // the rows the SOV chain needs, scaled by the diagonal:
-//     row a (a = 0..k):  L_a0/L_aa, ..., L_a,a-1/L_aa, b_a/L_aa
+//     row a (a = 0..K):  L_a0/L_aa, ..., L_a,a-1/L_aa, b_a/L_aa
 // at offset a(a+1)/2 of the term's block, so that t_a = b_a/L_aa - sum_c (L_ac/L_aa) y_c.
-// It also stores Phi(b_0/L_00), the exact value of a term with k = 0.
+// It also stores Phi(b_0/L_00), the exact value of a term with K = 0.
+//
+// Censored plans (Section 4, eq. (11)): plan positions below n_obs are sites
+// whose value is observed. Their q neighbours among those sites are placed
+// first, then the censored neighbours, then i. With E the first q variables,
+// the lower-right block of L is the Cholesky factor of the covariance of the
+// rest given X_E = b_E, and their conditional mean is L_{A,E} w with
+// w = L_EE^-1 b_E; the rows written are those of the rest, with b_a replaced by
+// b_a - sum_{c<q} L_ac w_c, so the chain runs in K = k - q dimensions. For an
+// observed site i every neighbour is observed (q = k) and the term is the
+// Gaussian conditional density of eq. (4) at scale r, times the Jacobian 1 / r:
+//     log f = -log(2 pi)/2 - log L_kk - z^2/2 + log(1/r),  z = (b_k - sum_{c<k} L_kc w_c) / L_kk.
+//
 // A pivot <= 0 (or NaN) marks the term NOT_PD: its outputs become NaN and the
 // instance's bad_term is lowered to i.
 #include "fp32_math_coeffs.h"
@@ -41,7 +53,7 @@ __global__ __launch_bounds__(64) void term_setup(const InstDesc* __restrict__ in
                                                  Aux64* __restrict__ aux64,
                                                  Aux32* __restrict__ aux32, int64_t term_base) {
   __shared__ double C[kMaxVars][kMaxVars + 1];
-  __shared__ double px[kMaxVars], py[kMaxVars], pb[kMaxVars];
+  __shared__ double px[kMaxVars], py[kMaxVars], pb[kMaxVars], pw[kMaxVars];
   __shared__ int pv[kMaxVars];
   __shared__ double piv;
   const int lane = threadIdx.x;
@@ -51,14 +63,21 @@ __global__ __launch_bounds__(64) void term_setup(const InstDesc* __restrict__ in
   const int64_t i = t - term_bases[ii];
   const int k = I.kcnt[i];
   const int n = k + 1;
+  // variable slot of each lane's neighbour: observed neighbours first (censored
+  // plans only), each group in the stored order, i last
+  const int64_t v = lane < k ? (int64_t)I.nbr[i * I.m + lane] : i;
+  const bool eq = lane < k && v < I.n_obs;
+  const uint64_t eq_mask = __ballot(eq);
+  const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  const int q = __popcll(eq_mask);
+  const int slot = lane >= k ? lane : eq ? __popcll(eq_mask & below) : q + (lane - __popcll(eq_mask & below));
   if (lane < n) {
-    const int64_t v = lane < k ? (int64_t)I.nbr[i * I.m + lane] : i;
-    pv[lane] = (int)v;
+    pv[slot] = (int)v;
     if (!I.covmat) {
-      px[lane] = I.xs[v];
-      py[lane] = I.ys[v];
+      px[slot] = I.xs[v];
+      py[slot] = I.ys[v];
     }
-    pb[lane] = I.x[I.perm[v]] * I.inv_scale;
+    pb[slot] = I.x[I.perm[v]] * I.inv_scale;
   }
   __syncthreads();
   for (int idx = lane; idx < n * n; idx += 64) {
@@ -94,44 +113,71 @@ __global__ __launch_bounds__(64) void term_setup(const InstDesc* __restrict__ in
     if (lane == j) C[j][j] = ljj;
     __syncthreads();
   }
+  // w = L_EE^-1 b_E (forward substitution, q <= k steps) and the shifted limits
+  if (lane == 0) {
+    for (int c = 0; c < q; ++c) {
+      double acc = pb[c];
+      for (int p = 0; p < c; ++p) acc -= C[c][p] * pw[p];
+      pw[c] = acc / C[c][c];
+    }
+  }
+  __syncthreads();
+  double bs = 0.0;
+  if (lane >= q && lane < n) {
+    bs = pb[lane];
+    for (int c = 0; c < q; ++c) bs -= C[lane][c] * pw[c];
+    pb[lane] = bs;
+  }
+  __syncthreads();
   const double nan = __builtin_nan("");
   const bool f32 = I.precision == VECCHIA_FP32_LOOP;
-  if (lane < n) {
+  const bool density = i < I.n_obs;
+  if (!density && lane >= q && lane < n) {
+    const int a = lane - q;   // row of the conditional block
     const double laa = C[lane][lane];
-    const int64_t off = i * (int64_t)I.prep_stride + (int64_t)lane * (lane + 1) / 2;
+    const int64_t off = i * (int64_t)I.prep_stride + (int64_t)a * (a + 1) / 2;
     if (f32) {
       // the FP32 loop works with v = kappa t (exp(-t^2/2) = 2^(-v^2))
       const double sc = kPhiScale / laa;
       float* row = reinterpret_cast<float*>(I.prep) + off;
-      for (int c = 0; c < lane; ++c) row[c] = (float)(C[lane][c] * sc);
-      row[lane] = bad ? __builtin_nanf("") : (float)(pb[lane] * sc);
+      for (int c = 0; c < a; ++c) row[c] = (float)(C[lane][q + c] * sc);
+      row[a] = bad ? __builtin_nanf("") : (float)(bs * sc);
     } else {
       double* row = reinterpret_cast<double*>(I.prep) + off;
-      for (int c = 0; c < lane; ++c) row[c] = C[lane][c] / laa;
-      row[lane] = bad ? nan : pb[lane] / laa;
+      for (int c = 0; c < a; ++c) row[c] = C[lane][q + c] / laa;
+      row[a] = bad ? nan : bs / laa;
     }
   }
   if (lane == 0) {
-    const double b0 = pb[0] / C[0][0];
-    const double e0 = bad ? nan : normcdf(b0);
-    aux64[t].e0 = e0;
-    aux64[t].lt0 = bad ? nan : log(e0);
-    if (f32) {
-      // e0 as em0 * 2^en0: split only below 2^-100 (the loop's first quantile
-      // argument w e0 then stays a normal FP32 number)
-      Aux32 a;
-      a.neg0 = b0 <= 0.0 ? 1.0f : 0.0f;
-      if (e0 < 0x1p-100) {
-        int ex = 0;
-        const double mt = frexp(e0, &ex);
-        a.em0 = (float)mt;
-        a.en0 = (float)ex;
-      } else {
-        a.em0 = (float)e0;
-        a.en0 = 0.0f;
+    if (density) {
+      const double lkk = C[k][k];
+      const double z = pb[k] / lkk;
+      const double lf = -0.91893853320467274178 - log(lkk) - 0.5 * z * z + log(I.inv_scale);
+      aux64[t].e0 = bad ? nan : exp(lf);
+      aux64[t].lt0 = bad ? nan : lf;
+      if (f32) aux32[t] = Aux32{0.0f, 0.0f, 0.0f, 0.0f};
+    } else {
+      const double b0 = pb[q] / C[q][q];
+      const double e0 = bad ? nan : normcdf(b0);
+      aux64[t].e0 = e0;
+      aux64[t].lt0 = bad ? nan : log(e0);
+      if (f32) {
+        // e0 as em0 * 2^en0: split only below 2^-100 (the loop's first quantile
+        // argument w e0 then stays a normal FP32 number)
+        Aux32 a;
+        a.neg0 = b0 <= 0.0 ? 1.0f : 0.0f;
+        if (e0 < 0x1p-100) {
+          int ex = 0;
+          const double mt = frexp(e0, &ex);
+          a.em0 = (float)mt;
+          a.en0 = (float)ex;
+        } else {
+          a.em0 = (float)e0;
+          a.en0 = 0.0f;
+        }
+        a.ec0 = bad ? __builtin_nanf("") : (float)normcdf(-b0);
+        aux32[t] = a;
       }
-      a.ec0 = bad ? __builtin_nanf("") : (float)normcdf(-b0);
-      aux32[t] = a;
     }
     if (bad) atomicMin((long long*)I.bad_term, (long long)i);
   }

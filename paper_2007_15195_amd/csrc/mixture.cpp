@@ -1,17 +1,21 @@
 // Gaussian scale mixture, the outer integral over the random scale R
-// (Section 4, eqs. (7)-(9)): G(x) = int Phi_D(x / r) f_R(r) dr, with F_R from
-// eq. (8) (beta > 0, or beta = 0 read as the Pareto law 1 - r^-gamma), r >= 1.
+// (Section 4, eqs. (7)-(9) and (11)): G(x) = int h(r) f_R(r) dr over r >= 1, with
+// F_R from eq. (8) (beta > 0, or beta = 0 read as the Pareto law 1 - r^-gamma)
+// and h(r) the plan's Vecchia value at scale r (Phi_D(x / r) for a plain plan,
+// the censored integrand L_r(x) of eq. (11) for a censored plan).
 //
 // With v = -log(1 - F_R(R)) ~ Exp(1), G = int_0^inf e^-v h(v) dv where
-// h(v) = Phi_D(x / r(v)), r(v) = e^(v/gamma) (beta = 0) or
-// (1 + beta v / gamma)^(1/beta), capped at 1e300. The rule has two passes:
-//   1. log h at v = 0 and v = 1e-3 (one batched evaluation of the plan at two
-//      scales) gives mu = 1 + max(0, -(log h(1e-3) - log h(0)) / 1e-3);
-//   2. n-node Gauss-Laguerre in tau = mu v (one batched evaluation at the n
-//      scales r(tau_k / mu)), G = sum_k w_k / mu e^(tau_k (1 - 1/mu)) h(tau_k / mu),
+// r(v) = e^(v/gamma) (beta = 0) or (1 + beta v / gamma)^(1/beta), capped at
+// 1e300. l(v) = log h(v) - v peaks at v = 0 for a plain CDF with positive
+// thresholds and inside (0, inf) for a censored likelihood, so the rule has two
+// batched passes:
+//   1. search: l at v = 0 and v_j = 1e-4 (2e6)^((j-1)/22), j = 1..23, with
+//      n_points / 16 lattice points (at least 64, a multiple of 64);
+//   2. window [lo, hi]: the search points nearest the maximum on each side whose
+//      l is more than 36 below it (else 0 and 200); n-point Gauss-Legendre on it,
+//      in s = log v when lo > 0 and hi / lo > 8, else in v, at the full size,
 //      combined in log space on the device.
-// Every node uses the call's seed (common random numbers). The rule is exact
-// when log h is linear in v (for instance x = 0, where G = Phi_D(0)).
+// Every node uses the call's seed (common random numbers).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -27,77 +31,51 @@
 namespace vecchia {
 namespace {
 
-constexpr double kDelta = 1e-3;
 constexpr double kRMax = 1e300;
+constexpr double kCut = 36.0;
+constexpr double kLogSpan = 8.0;
+constexpr double kVMax = 200.0;
 
 double mixture_scale(double v, double beta, double gamma) {
   const double s = beta == 0.0 ? v / gamma : std::log1p(beta * v / gamma) / beta;
   return s >= std::log(kRMax) ? kRMax : std::exp(s);
 }
 
-// L_n(x) and L_n'(x) from the three-term recurrence
-// (k + 1) L_{k+1} = (2k + 1 - x) L_k - k L_{k-1} and x L_n' = n (L_n - L_{n-1}).
-void laguerre_eval(int n, double x, double* Ln, double* dLn) {
-  double p0 = 1.0, p1 = 1.0 - x;
-  for (int k = 1; k < n; ++k) {
-    const double p2 = ((2.0 * k + 1.0 - x) * p1 - k * p0) / (k + 1.0);
-    p0 = p1;
-    p1 = p2;
-  }
-  *Ln = p1;
-  *dLn = n * (p1 - p0) / x;
-}
+double search_v(int j) { return j == 0 ? 0.0 : 1e-4 * std::pow(2e6, (j - 1) / 22.0); }
 
-// Gauss-Laguerre rule for int_0^inf e^-t g(t) dt. Nodes: eigenvalues of the
-// symmetric Jacobi matrix of the Laguerre recurrence (diagonal 2k + 1,
-// off-diagonal k + 1; Golub-Welsch) by cyclic Jacobi rotations, then refined by
-// Newton steps on L_n. Weights: 1 / (t_k L_n'(t_k)^2).
-void laguerre_rule(int n, std::vector<double>* t, std::vector<double>* w) {
-  std::vector<double> A((size_t)n * n, 0.0);
-  auto a = [&](int i, int j) -> double& { return A[(size_t)i * n + j]; };
+int search_points(int n_points) { return std::max(64, ((n_points / 16 + 63) / 64) * 64); }
+
+// Gauss-Legendre nodes t_k (ascending) and weights on [-1, 1]: Newton on P_n from
+// t = cos(pi (k + 3/4) / (n + 1/2)), P_n and P_n' by the three-term recurrence
+// (j + 1) P_{j+1} = (2j + 1) t P_j - j P_{j-1} and (1 - t^2) P_n' = n (P_{n-1} - t P_n);
+// w_k = 2 / ((1 - t_k^2) P_n'(t_k)^2).
+void legendre_rule(int n, double* t, double* w) {
   for (int k = 0; k < n; ++k) {
-    a(k, k) = 2.0 * k + 1.0;
-    if (k + 1 < n) a(k, k + 1) = a(k + 1, k) = k + 1.0;
-  }
-  for (int sweep = 0; sweep < 100; ++sweep) {
-    double off = 0.0, diag = 0.0;
-    for (int i = 0; i < n; ++i) {
-      diag += a(i, i) * a(i, i);
-      for (int j = i + 1; j < n; ++j) off += a(i, j) * a(i, j);
-    }
-    if (off <= 1e-34 * diag) break;
-    for (int p = 0; p < n; ++p) {
-      for (int q = p + 1; q < n; ++q) {
-        const double apq = a(p, q);
-        if (apq == 0.0) continue;
-        const double theta = (a(q, q) - a(p, p)) / (2.0 * apq);
-        const double tt = (theta >= 0.0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
-        const double c = 1.0 / std::sqrt(tt * tt + 1.0), s = tt * c;
-        for (int r = 0; r < n; ++r) {
-          if (r == p || r == q) continue;
-          const double arp = a(r, p), arq = a(r, q);
-          a(r, p) = a(p, r) = c * arp - s * arq;
-          a(r, q) = a(q, r) = s * arp + c * arq;
-        }
-        a(p, p) -= tt * apq;
-        a(q, q) += tt * apq;
-        a(p, q) = a(q, p) = 0.0;
+    double x = std::cos(M_PI * (k + 0.75) / (n + 0.5));
+    double dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = x;
+      for (int j = 1; j < n; ++j) {
+        const double p2 = ((2.0 * j + 1.0) * x * p1 - j * p0) / (j + 1.0);
+        p0 = p1;
+        p1 = p2;
       }
+      dp = n * (p0 - x * p1) / (1.0 - x * x);
+      const double dx = p1 / dp;
+      x -= dx;
+      if (std::fabs(dx) <= 1e-16 * std::max(1.0, std::fabs(x))) break;
     }
-  }
-  t->resize(n);
-  w->resize(n);
-  for (int k = 0; k < n; ++k) (*t)[k] = a(k, k);
-  std::sort(t->begin(), t->end());
-  for (int k = 0; k < n; ++k) {
-    double x = (*t)[k], L = 0.0, dL = 1.0;
-    for (int it = 0; it < 4; ++it) {
-      laguerre_eval(n, x, &L, &dL);
-      x -= L / dL;
+    {
+      double p0 = 1.0, p1 = x;
+      for (int j = 1; j < n; ++j) {
+        const double p2 = ((2.0 * j + 1.0) * x * p1 - j * p0) / (j + 1.0);
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (p0 - x * p1) / (1.0 - x * x);
     }
-    laguerre_eval(n, x, &L, &dL);
-    (*t)[k] = x;
-    (*w)[k] = 1.0 / (x * dL * dL);
+    t[n - 1 - k] = x;
+    w[n - 1 - k] = 2.0 / ((1.0 - x * x) * dp * dp);
   }
 }
 
@@ -110,12 +88,44 @@ bool valid_mixture(const vecchia_mixture* m, std::string* why) {
   return true;
 }
 
-void rule_for(const vecchia_mixture& m, double mu, double* scales, double* logw) {
-  std::vector<double> t, w;
-  laguerre_rule(m.n_nodes, &t, &w);
+// Window of step 2 from the search values log h(v_j); a NaN value gives a NaN window.
+void window_for(const double* search_logh, double* lo, double* hi) {
+  double ell[kMixSearch];
+  int j = 0;
+  for (int i = 0; i < kMixSearch; ++i) {
+    ell[i] = search_logh[i] - search_v(i);
+    if (std::isnan(ell[i])) {
+      *lo = *hi = std::nan("");
+      return;
+    }
+    if (ell[i] > ell[j]) j = i;
+  }
+  const double top = ell[j];
+  *lo = 0.0;
+  *hi = kVMax;
+  for (int i = j - 1; i >= 0; --i)
+    if (ell[i] < top - kCut) {
+      *lo = search_v(i);
+      break;
+    }
+  for (int i = j + 1; i < kMixSearch; ++i)
+    if (ell[i] < top - kCut) {
+      *hi = search_v(i);
+      break;
+    }
+}
+
+void rule_for(const vecchia_mixture& m, double lo, double hi, double* v, double* scales, double* logw) {
+  double t[kMaxMixNodes], w[kMaxMixNodes];
+  legendre_rule(m.n_nodes, t, w);
+  const bool logmap = lo > 0.0 && hi / lo > kLogSpan;
+  const double a = logmap ? std::log(lo) : lo, b = logmap ? std::log(hi) : hi;
   for (int k = 0; k < m.n_nodes; ++k) {
-    scales[k] = mixture_scale(t[k] / mu, m.beta, m.gamma);
-    logw[k] = std::log(w[k]) - std::log(mu) + t[k] * (1.0 - 1.0 / mu);
+    const double u = a + (b - a) * (t[k] + 1.0) / 2.0;
+    const double vk = logmap ? std::exp(u) : u;
+    v[k] = vk;
+    scales[k] = mixture_scale(vk, m.beta, m.gamma);
+    logw[k] = std::log(w[k] * (b - a) / 2.0) + (logmap ? u : 0.0) - vk;
   }
 }
 
@@ -139,13 +149,28 @@ vecchia_status ensure_batch(vecchia_plan_s* P, std::unique_ptr<Batch>* slot, int
 
 extern "C" {
 
-vecchia_status vecchia_mixture_rule(const vecchia_mixture* mix, double mu, double* scales_out, double* logw_out) {
+vecchia_status vecchia_mixture_search(const vecchia_mixture* mix, double* scales_out) {
   using namespace vecchia;
   std::string why;
   if (!valid_mixture(mix, &why)) return set_error(VECCHIA_E_INVALID, why);
-  if (!(std::isfinite(mu) && mu >= 1.0) || !scales_out || !logw_out)
-    return set_error(VECCHIA_E_INVALID, "mu must be finite and >= 1; outputs must hold n_nodes values");
-  rule_for(*mix, mu, scales_out, logw_out);
+  if (!scales_out) return set_error(VECCHIA_E_INVALID, "scales_out must hold VECCHIA_MIX_SEARCH_NODES values");
+  for (int j = 0; j < kMixSearch; ++j) scales_out[j] = mixture_scale(search_v(j), mix->beta, mix->gamma);
+  return VECCHIA_OK;
+}
+
+vecchia_status vecchia_mixture_rule(const vecchia_mixture* mix, const double* search_logh, double* window_out,
+                                    double* v_out, double* scales_out, double* logw_out) {
+  using namespace vecchia;
+  std::string why;
+  if (!valid_mixture(mix, &why)) return set_error(VECCHIA_E_INVALID, why);
+  if (!search_logh || !window_out || !v_out || !scales_out || !logw_out)
+    return set_error(VECCHIA_E_INVALID, "null pointer");
+  double lo, hi;
+  window_for(search_logh, &lo, &hi);
+  window_out[0] = lo;
+  window_out[1] = hi;
+  if (std::isnan(lo)) return set_error(VECCHIA_E_INVALID, "a search value is NaN");
+  rule_for(*mix, lo, hi, v_out, scales_out, logw_out);
   return VECCHIA_OK;
 }
 
@@ -159,38 +184,44 @@ vecchia_status vecchia_mixture_logcdf(vecchia_plan_t plan, const double* x_dev, 
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   std::lock_guard<std::mutex> lk(plan->mu);
   if (!plan->d_mix) {
-    hipError_t e = hipMalloc(&plan->d_mix, sizeof(double) * 2 * (2 + kMaxMixNodes));
+    hipError_t e = hipMalloc(&plan->d_mix, sizeof(double) * 2 * (kMixSearch + kMaxMixNodes));
     if (e != hipSuccess) {
       plan->d_mix = nullptr;
       return hip_error(e, "mixture buffer");
     }
   }
   const int n = mix->n_nodes;
+  const int nmax = std::max(kMixSearch, n);
   std::vector<vecchia_cov> covs;
-  if (cov_override) covs.assign((size_t)std::max(2, n), *cov_override);
-  std::vector<uint64_t> seeds((size_t)std::max(2, n), q->seed);
-  // pass 1: log h at v = 0 and v = delta
-  vecchia_status st = ensure_batch(plan, &plan->mix1, 2, *q);
+  if (cov_override) covs.assign((size_t)nmax, *cov_override);
+  std::vector<uint64_t> seeds((size_t)nmax, q->seed);
+  // pass 1: the search at n_points / 16
+  vecchia_qmc qs = *q;
+  qs.n_points = search_points(q->n_points);
+  vecchia_status st = ensure_batch(plan, &plan->mix1, kMixSearch, qs);
   if (st != VECCHIA_OK) return st;
-  const double sc1[2] = {1.0, mixture_scale(kDelta, mix->beta, mix->gamma)};
+  double sc1[kMixSearch];
+  for (int j = 0; j < kMixSearch; ++j) sc1[j] = mixture_scale(search_v(j), mix->beta, mix->gamma);
   st = plan->mix1->run(x_dev, sc1, cov_override ? covs.data() : nullptr, plan->d_mix, nullptr, seeds.data(), s);
   if (st != VECCHIA_OK) return st;
-  double h[4] = {0, 0, 0, 0};
+  double h[2 * kMixSearch];
   hipError_t e = hipMemcpyAsync(h, plan->d_mix, sizeof(h), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  if (e != hipSuccess) return hip_error(e, "mixture first pass");
-  double mu = 1.0 + std::max(0.0, -(h[2] - h[0]) / kDelta);
-  if (!std::isfinite(mu)) mu = 1.0;   // a non-finite node value propagates through the combination
-  // pass 2: the Laguerre nodes
-  std::vector<double> scales(n);
+  if (e != hipSuccess) return hip_error(e, "mixture search pass");
+  double logh[kMixSearch];
+  for (int j = 0; j < kMixSearch; ++j) logh[j] = h[2 * j];
+  double lo, hi;
+  window_for(logh, &lo, &hi);
+  if (std::isnan(lo)) lo = 0.0, hi = kVMax;   // a NaN node value propagates through the combination
+  // pass 2: Gauss-Legendre on the window
+  double v[kMaxMixNodes], scales[kMaxMixNodes];
   MixWeights mw{};
   mw.n = n;
-  rule_for(*mix, mu, scales.data(), mw.logw);
+  rule_for(*mix, lo, hi, v, scales, mw.logw);
   st = ensure_batch(plan, &plan->mix2, n, *q);
   if (st != VECCHIA_OK) return st;
-  double* node_out = plan->d_mix + 4;
-  st = plan->mix2->run(x_dev, scales.data(), cov_override ? covs.data() : nullptr, node_out, nullptr, seeds.data(),
-                       s);
+  double* node_out = plan->d_mix + 2 * kMixSearch;
+  st = plan->mix2->run(x_dev, scales, cov_override ? covs.data() : nullptr, node_out, nullptr, seeds.data(), s);
   if (st != VECCHIA_OK) return st;
   e = launch_mixture_combine(node_out, mw, out_dev, nodes_dev, s);
   if (e != hipSuccess) return hip_error(e, "mixture combination");

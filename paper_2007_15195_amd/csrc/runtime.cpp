@@ -225,6 +225,8 @@ vecchia_status Batch::create(const std::vector<vecchia_plan_s*>& plans,
     d.perm = P->d_perm;
     d.nbr = P->d_nbr;
     d.kcnt = P->d_kcnt;
+    d.sovk = P->n_obs > 0 ? P->d_sovk : P->d_kcnt;
+    d.n_obs = P->n_obs;
     d.D = P->D;
     d.term_base = tb;
     d.sums_base = sb;
@@ -242,11 +244,12 @@ vecchia_status Batch::create(const std::vector<vecchia_plan_s*>& plans,
     prep += align_up((size_t)P->D * stride * (prec == VECCHIA_FP32_LOOP ? 4 : 8), 256);
     if (prec == VECCHIA_FP32_LOOP) b->any_f32_ = true;
     // runs of equal k >= 1 become ranges of the launch for that k
+    const std::vector<int32_t>& sk = P->sov_dims();
     int64_t i = 0;
     while (i < P->D) {
-      const int k = P->kcnt[i];
+      const int k = sk[i];
       int64_t e = i + 1;
-      while (e < P->D && P->kcnt[e] == k) ++e;
+      while (e < P->D && sk[e] == k) ++e;
       if (k >= 1) {
         RangeDesc r;
         r.item_begin = e - i;   // term count; turned into the item prefix below
@@ -450,7 +453,7 @@ vecchia_status Batch::run(const double* x_dev, const double* scales, const vecch
     // every address a kernel dereferences must be set before anything is enqueued
     const InstDesc& q = d[j];
     const bool geom_ok = q.covmat || (q.xs && q.ys);
-    if (!q.prep || !q.bad_term || !q.x || !q.out || !q.kcnt || !q.perm || !geom_ok ||
+    if (!q.prep || !q.bad_term || !q.x || !q.out || !q.kcnt || !q.sovk || !q.perm || !geom_ok ||
         (q.m > 0 && !q.nbr) || !d_desc_ || !d_term_bases_ || !d_ranges_ || !d_aux64_ || !d_sums_ ||
         !d_Z_ || (any_f32_ && !d_aux32_))
       return set_error(VECCHIA_E_HIP, "internal error: incomplete device descriptor");

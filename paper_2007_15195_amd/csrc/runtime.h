@@ -138,6 +138,13 @@ struct vecchia_plan_s {
   bool matrix = false;
   std::vector<int64_t> perm;       // plan position -> user index
   std::vector<int32_t> kcnt;       // host copy of k_i
+  // censored plans (eq. (11)): plan positions < n_obs are the uncensored sites;
+  // sovk[i] is the SOV dimension of term i (0 for a density term, else the
+  // number of censored neighbours); empty with n_obs = 0
+  int64_t n_obs = 0;
+  std::vector<int32_t> sovk;
+  int32_t* d_sovk = nullptr;
+  const std::vector<int32_t>& sov_dims() const { return n_obs > 0 ? sovk : kcnt; }
   double* d_xs = nullptr;
   double* d_ys = nullptr;
   double* d_cov = nullptr;

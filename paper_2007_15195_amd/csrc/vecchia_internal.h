@@ -23,11 +23,13 @@ struct InstDesc {
   const int32_t* perm;     // plan position -> user index
   const int32_t* nbr;      // D x m conditioning sets (plan indices), -1 padded
   const int32_t* kcnt;     // D: size k_i of each conditioning set
+  const int32_t* sovk;     // D: SOV dimension of each term (= kcnt unless censored)
   const double* x;         // thresholds, user order
   double* out;             // {log F, SE}
   double* terms_out;       // D x 2 user order, or null
   void* prep;              // per-term scaled Cholesky rows (double or float), term 0
   int64_t D;
+  int64_t n_obs;           // plan positions < n_obs are uncensored sites (eq. (11)); 0 = plain
   int64_t term_base;       // global index of plan term 0 (aux arrays)
   int64_t sums_base;       // index of (term 0, shift 0, chunk 0) in the sums triples
   int64_t* bad_term;       // first plan-order term whose Cholesky failed (min)
@@ -87,6 +89,7 @@ hipError_t launch_qmc(int K, int precision, const InstDesc* d_insts, const Range
                       const uint64_t* d_Z, double* sums, hipStream_t s);
 // Scale-mixture quadrature weights (log), passed by value to the combine kernel.
 constexpr int kMaxMixNodes = 64;
+constexpr int kMixSearch = VECCHIA_MIX_SEARCH_NODES;
 struct MixWeights {
   double logw[kMaxMixNodes];
   int32_t n;

@@ -32,7 +32,8 @@ EXPORTED = [
     "vecchia_batch_destroy", "vecchia_server_create", "vecchia_submit", "vecchia_poll",
     "vecchia_server_destroy", "vecchia_profile_enable", "vecchia_profile_read", "vecchia_profile_reset",
     "vecchia_autotune", "vecchia_tuning_get", "vecchia_tuning_set", "vecchia_calibrate_valu",
-    "vecchia_mixture_logcdf", "vecchia_mixture_rule",
+    "vecchia_mixture_logcdf", "vecchia_mixture_rule", "vecchia_mixture_search",
+    "vecchia_plan_censored", "vecchia_plan_from_cov_censored", "vecchia_plan_censoring",
 ]
 
 
@@ -73,6 +74,11 @@ def lib():
         "vecchia_plan": [c_void_p, c_int64, c_int32, c_int32, c_void_p, c_int32, POINTER(vecchia_cov),
                          c_void_p, POINTER(c_void_p)],
         "vecchia_plan_from_cov": [c_void_p, c_int64, c_void_p, c_int32, c_void_p, POINTER(c_void_p)],
+        "vecchia_plan_censored": [c_void_p, c_int64, c_int32, c_int32, c_void_p, c_void_p, c_int32,
+                                  POINTER(vecchia_cov), c_void_p, POINTER(c_void_p)],
+        "vecchia_plan_from_cov_censored": [c_void_p, c_int64, c_void_p, c_int32, c_int64, c_void_p,
+                                           POINTER(c_void_p)],
+        "vecchia_plan_censoring": [c_void_p, POINTER(c_int64)],
         "vecchia_replan": [c_void_p, c_void_p, c_int32, c_void_p, c_void_p],
         "vecchia_plan_info": [c_void_p, POINTER(c_int64), POINTER(c_int32)],
         "vecchia_plan_neighbours": [c_void_p, c_void_p, c_void_p],
@@ -99,7 +105,8 @@ def lib():
         "vecchia_calibrate_valu": [c_void_p, c_void_p],
         "vecchia_mixture_logcdf": [c_void_p, c_void_p, POINTER(vecchia_mixture), c_void_p, POINTER(vecchia_qmc),
                                    c_void_p, c_void_p, c_void_p],
-        "vecchia_mixture_rule": [POINTER(vecchia_mixture), c_double, c_void_p, c_void_p],
+        "vecchia_mixture_rule": [POINTER(vecchia_mixture), c_void_p, c_void_p, c_void_p, c_void_p, c_void_p],
+        "vecchia_mixture_search": [POINTER(vecchia_mixture), c_void_p],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -181,19 +188,59 @@ def vecchia_plan(locs: np.ndarray, ordering: int, m: int, cov, perm=None, stream
     return h.value
 
 
+def _nbr_table(nbr, D: int, m: int):
+    if nbr is None:
+        return None
+    nb = np.full((D, m), -1, dtype=np.int32)
+    for i, row in enumerate(nbr):
+        row = list(row)
+        nb[i, :len(row)] = row
+    return nb
+
+
 def vecchia_plan_from_cov(Sigma: np.ndarray, m: int, nbr=None, stream=None) -> int:
     Sigma = np.ascontiguousarray(Sigma, dtype=np.float64)
     D = Sigma.shape[0]
-    nb = None
-    if nbr is not None:
-        nb = np.full((D, m), -1, dtype=np.int32)
-        for i, row in enumerate(nbr):
-            row = list(row)
-            nb[i, :len(row)] = row
+    nb = _nbr_table(nbr, D, m)
     h = c_void_p()
     _check(lib().vecchia_plan_from_cov(Sigma.ctypes.data, D, None if nb is None else nb.ctypes.data,
                                        int(m), _stream_ptr(stream), byref(h)))
     return h.value
+
+
+def vecchia_plan_censored(locs: np.ndarray, observed, ordering: int, m: int, cov, perm=None,
+                          stream=None) -> int:
+    """Censored plan of one replicate: observed[u] true where site u's value is
+    observed (eq. (11)); those sites are ordered first."""
+    locs = np.ascontiguousarray(locs, dtype=np.float64)
+    if locs.ndim != 2:
+        raise ValueError("locs must be D x dim")
+    obs = np.ascontiguousarray(np.asarray(observed, dtype=bool), dtype=np.uint8)
+    if obs.shape != (locs.shape[0],):
+        raise ValueError("observed must hold one flag per location")
+    pin = None if perm is None else np.ascontiguousarray(perm, dtype=np.int64)
+    h = c_void_p()
+    c = as_cov(cov)
+    _check(lib().vecchia_plan_censored(locs.ctypes.data, locs.shape[0], locs.shape[1], int(ordering),
+                                       None if pin is None else pin.ctypes.data, obs.ctypes.data, int(m),
+                                       byref(c), _stream_ptr(stream), byref(h)))
+    return h.value
+
+
+def vecchia_plan_from_cov_censored(Sigma: np.ndarray, m: int, n_observed: int, nbr=None, stream=None) -> int:
+    Sigma = np.ascontiguousarray(Sigma, dtype=np.float64)
+    D = Sigma.shape[0]
+    nb = _nbr_table(nbr, D, m)
+    h = c_void_p()
+    _check(lib().vecchia_plan_from_cov_censored(Sigma.ctypes.data, D, None if nb is None else nb.ctypes.data,
+                                                int(m), int(n_observed), _stream_ptr(stream), byref(h)))
+    return h.value
+
+
+def vecchia_plan_censoring(plan: int) -> int:
+    n = c_int64()
+    _check(lib().vecchia_plan_censoring(plan, byref(n)))
+    return n.value
 
 
 def vecchia_replan(plan: int, locs: np.ndarray, ordering: int, perm=None, stream=None) -> None:
@@ -344,17 +391,35 @@ def vecchia_calibrate_valu(stream=None) -> dict:
     return dict(zip(("fma", "exp", "log", "rcp", "sqrt"), list(r)))
 
 
-def make_mixture(beta: float = 0.0, gamma: float = 2.0, n_nodes: int = 32) -> vecchia_mixture:
+MIX_SEARCH_NODES = 24
+
+
+def make_mixture(beta: float = 0.0, gamma: float = 2.0, n_nodes: int = 48) -> vecchia_mixture:
     return vecchia_mixture(float(beta), float(gamma), int(n_nodes), 0)
 
 
-def vecchia_mixture_rule(mix: vecchia_mixture, mu: float):
-    """(scales, log weights) of the pass-2 rule for a given mu (host only)."""
+def vecchia_mixture_search(mix: vecchia_mixture):
+    """Scales of the first (search) pass (host only)."""
+    sc = np.empty(MIX_SEARCH_NODES, dtype=np.float64)
+    _check(lib().vecchia_mixture_search(byref(mix), sc.ctypes.data))
+    return sc
+
+
+def vecchia_mixture_rule(mix: vecchia_mixture, search_logh):
+    """(window, v, scales, log weights) of the second-pass rule for given search
+    values log h(v_j) (host only)."""
+    h = np.ascontiguousarray(search_logh, dtype=np.float64)
+    if h.shape != (MIX_SEARCH_NODES,):
+        raise ValueError(f"need {MIX_SEARCH_NODES} search values")
+    n = max(1, int(mix.n_nodes))
+    win = np.empty(2, dtype=np.float64)
+    v = np.empty(n, dtype=np.float64)
+    sc = np.empty(n, dtype=np.float64)
+    lw = np.empty(n, dtype=np.float64)
+    _check(lib().vecchia_mixture_rule(byref(mix), h.ctypes.data, win.ctypes.data, v.ctypes.data, sc.ctypes.data,
+                                      lw.ctypes.data))
     n = int(mix.n_nodes)
-    sc = np.empty(max(1, n), dtype=np.float64)
-    lw = np.empty(max(1, n), dtype=np.float64)
-    _check(lib().vecchia_mixture_rule(byref(mix), float(mu), sc.ctypes.data, lw.ctypes.data))
-    return sc[:n], lw[:n]
+    return (float(win[0]), float(win[1])), v[:n], sc[:n], lw[:n]
 
 
 def vecchia_mixture_logcdf(plan: int, x, mix: vecchia_mixture, qmc, out, nodes=None, cov_override=None,

@@ -92,6 +92,19 @@ def test_plan_rejects_bad_arguments_before_gpu_work():
         V.vecchia_plan_from_cov(np.array([[1.0, 0.5], [0.4, 1.0]]), 1, stream=0)   # not symmetric
     with pytest.raises(V.VecchiaError):
         V.vecchia_plan_from_cov(np.eye(3), 2, nbr=[[], [0], [2]], stream=0)      # not preceding
+    obs = np.array([1, 0, 0, 1, 0], dtype=bool)
+    with pytest.raises(V.VecchiaError):
+        V.vecchia_plan_censored(locs, obs, W.ORDER_COORD, 32, cov, stream=0)
+    with pytest.raises(ValueError):
+        V.vecchia_plan_censored(locs, obs[:4], W.ORDER_COORD, 2, cov, stream=0)
+    bad = np.array([1, 0, 2, 0, 0], dtype=np.uint8)
+    with pytest.raises(V.VecchiaError):
+        V._check(V.lib().vecchia_plan_censored(locs.ctypes.data, 5, 2, W.ORDER_COORD, None, bad.ctypes.data, 2,
+                                               V.byref(cov), None, V.byref(V.c_void_p())))
+    with pytest.raises(V.VecchiaError):
+        V.vecchia_plan_from_cov_censored(np.eye(3), 2, 4, stream=0)              # n_observed > D
+    with pytest.raises(V.VecchiaError):
+        V.vecchia_plan_from_cov_censored(np.eye(3), 2, -1, stream=0)
     with pytest.raises(V.VecchiaError) as e:
         V.vecchia_server_create(0, 4)
     assert e.value.status == 1
@@ -126,18 +139,35 @@ def test_calibration_hook_rejects_missing_output():
     assert e.value.status == 1
 
 
+def _search_profiles():
+    # log h on the search grid: a plain CDF (bulk at v = 0), a censored-like
+    # interior peak (narrow and wide), a flat profile and one that sits at -inf
+    # on part of the grid
+    v = np.array([0.0] + [1e-4 * 2e6 ** ((j - 1) / 22) for j in range(1, 24)])
+    yield np.log1p(-0.5 * (1 - np.exp(-40.0 * v))) * 300.0
+    yield 60.0 * (1 - np.exp(-v)) - 4.0 * v
+    yield 400.0 * (1 - np.exp(-3.0 * v)) - 30.0 * v
+    yield np.full(24, -3.0)
+    yield np.where(v < 1.0, -np.inf, -2.0 * v)
+
+
 @pytest.mark.parametrize("beta,gamma", [(0.0, 2.0), (0.0, 0.3), (0.5, 1.0), (2.0, 0.5)])
-@pytest.mark.parametrize("n", [1, 2, 8, 32, 64])
-@pytest.mark.parametrize("mu", [1.0, 1.37, 195.0])
-def test_mixture_rule_matches_the_oracle(beta, gamma, n, mu):
-    # the library's own Gauss-Laguerre rule and scale map against the oracle's
-    # (numpy's laggauss and the inverse of eq. (8))
+@pytest.mark.parametrize("n", [1, 2, 8, 48, 64])
+def test_mixture_rule_matches_the_oracle(beta, gamma, n):
+    # the library's search scales, window and Gauss-Legendre rule against the
+    # oracle's (numpy's leggauss and the inverse of eq. (8))
     from oracle import mixture as M
-    sc, lw = V.vecchia_mixture_rule(V.make_mixture(beta, gamma, n), mu)
-    osc, olw = M.pass2(mu, n, beta, gamma)
-    np.testing.assert_allclose(sc, osc, rtol=1e-12, atol=0.0)
-    big = olw > -600.0            # weights below e^-600 do not contribute to any sum
-    np.testing.assert_allclose(lw[big], olw[big], rtol=0.0, atol=1e-9)
+    mix = V.make_mixture(beta, gamma, n)
+    osc = np.array([M.scale_at(v, beta, gamma) for v in M.search_v()])
+    np.testing.assert_allclose(V.vecchia_mixture_search(mix), osc, rtol=1e-13, atol=0.0)
+    for h in _search_profiles():
+        win, v, sc, lw = V.vecchia_mixture_rule(mix, h)
+        owin = M.window(h)
+        assert win == owin
+        ov, olw = M.legendre_rule(owin[0], owin[1], n)
+        np.testing.assert_allclose(v, ov, rtol=1e-13, atol=1e-300)
+        np.testing.assert_allclose(sc, [M.scale_at(float(x), beta, gamma) for x in ov], rtol=1e-12, atol=0.0)
+        np.testing.assert_allclose(lw, olw, rtol=1e-13, atol=1e-12)
 
 
 def test_mixture_arguments_rejected_on_the_host():
@@ -145,7 +175,18 @@ def test_mixture_arguments_rejected_on_the_host():
     for mix in (V.make_mixture(-0.1, 2.0, 8), V.make_mixture(0.0, 0.0, 8), V.make_mixture(0.0, 2.0, 0),
                 V.make_mixture(0.0, 2.0, 65), V.make_mixture(float("nan"), 2.0, 8)):
         with pytest.raises(V.VecchiaError) as e:
-            V.vecchia_mixture_rule(mix, 1.0)
+            V.vecchia_mixture_rule(mix, np.zeros(24))
         assert e.value.status == 1
     with pytest.raises(V.VecchiaError):
-        V.vecchia_mixture_rule(V.make_mixture(0.0, 2.0, 8), 0.5)      # mu < 1
+        V.vecchia_mixture_rule(V.make_mixture(0.0, 2.0, 8), np.full(24, np.nan))   # NaN search value
+
+
+def test_censored_matrix_plan_host_setup_runs_before_device_work():
+    # the host part of a censored matrix plan (neighbour lists, k_i, SOV
+    # dimensions) runs before any device allocation; without a device the call
+    # then fails with an error instead of returning a plan
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a device is present: the GPU tests build these plans")
+    with pytest.raises(V.VecchiaError):
+        V.vecchia_plan_from_cov_censored(np.eye(4), 3, 2, nbr=[[], [0], [0, 1], [1, 2]], stream=0)

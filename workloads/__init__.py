@@ -204,3 +204,53 @@ def small_random_instance(D: int, m: int, seed: int, ordering: int = ORDER_MAXMI
     return Instance(f"small_D{D}_m{m}_s{seed}", locs, x, m, ordering,
                     Cov(family, nu, 1.0, rho, nugget),
                     QMC(n_points, n_shifts, seed + 7, precision), scale=scale)
+
+
+# ---------------------------------------------------------------------------
+# Censored replicates (Section 4: the censored likelihood of eq. (11)).
+# ---------------------------------------------------------------------------
+
+@dataclass
+class CensoredReplicate:
+    """One replicate: sites, thresholds and which values are observed.
+
+    x[u] is the censoring threshold at a censored site and the observed value
+    (above the threshold) at an observed site."""
+    inst: Instance
+    observed: np.ndarray          # D bools, user order
+
+
+def smooth_field(locs: np.ndarray, rng: np.random.Generator, nu: float, rho: float,
+                 n_features: int = 4000) -> np.ndarray:
+    """A stationary, approximately Gaussian random field with unit variance
+    and a Matern-like correlation scale rho, by random Fourier features:
+    X(s) = sqrt(2 / J) sum_j cos(w_j . s + b_j), w_j = t_j / rho with t_j
+    bivariate Student-t (2 nu degrees of freedom), b_j uniform on [0, 2 pi).
+    Used only to draw plausible replicates (spatially coherent exceedances)."""
+    g = rng.standard_normal((n_features, 2))
+    chi = rng.chisquare(2.0 * nu, n_features)
+    w = g / np.sqrt(chi / (2.0 * nu))[:, None] / rho
+    b = rng.uniform(0.0, 2.0 * np.pi, n_features)
+    return np.sqrt(2.0 / n_features) * np.cos(locs @ w.T + b).sum(axis=1)
+
+
+def censored_replicate(D: int, m: int, seed: int, frac_obs: float = 0.05, ordering: int = ORDER_MAXMIN,
+                       nu: float = 1.5, rho: float = 0.15, n_points: int = 512, n_shifts: int = 4,
+                       precision: int = PREC_FP64, nugget: float = 1e-8, family: int = COV_MATERN,
+                       min_obs: int = 1) -> CensoredReplicate:
+    """Uniform sites and one draw of a smooth field (smooth_field, same nu and
+    rho as the model) censored at its (1 - frac_obs) normal quantile u: sites
+    above u are observed with their value, the others sit at u (at least
+    min_obs sites observed: the largest values)."""
+    from statistics import NormalDist
+    rng = np.random.Generator(np.random.PCG64(seed))
+    locs = uniform_locations(D, rng)
+    X = smooth_field(locs, rng, nu if family == COV_MATERN else 0.5, rho)
+    u = NormalDist().inv_cdf(1.0 - frac_obs)
+    obs = X > u
+    if obs.sum() < min_obs:
+        obs[np.argsort(-X)[:min_obs]] = True
+    x = np.where(obs, np.maximum(X, u), u)
+    inst = Instance(f"censored_D{D}_m{m}_s{seed}", locs, x, m, ordering, Cov(family, nu, 1.0, rho, nugget),
+                    QMC(n_points, n_shifts, seed + 7, precision))
+    return CensoredReplicate(inst, obs)
