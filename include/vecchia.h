@@ -39,6 +39,7 @@ extern "C" {
 typedef struct vecchia_plan_s* vecchia_plan_t;
 typedef struct vecchia_batch_s* vecchia_batch_t;
 typedef struct vecchia_server_s* vecchia_server_t;
+typedef struct vecchia_mixbatch_s* vecchia_mixbatch_t;
 
 typedef enum {
   VECCHIA_OK = 0,
@@ -270,6 +271,38 @@ vecchia_status vecchia_mixture_search(const vecchia_mixture* mix, double* scales
  * Errors: INVALID (bad mixture, a NaN search value). */
 vecchia_status vecchia_mixture_rule(const vecchia_mixture* mix, const double* search_logh, double* window_out,
                                     double* v_out, double* scales_out, double* logw_out);
+
+/* Scale mixtures of many plans in one go: the censored log-likelihood of
+ * Section 4 is sum_t log G_{I_t}(x_t) over replicates t, each G_{I_t} the
+ * vecchia_mixture_logcdf of replicate t's censored plan. Create once per set
+ * of plans (n >= 1; n_nodes in 1..64; q: QMC size and precision, shared; the
+ * seed of replicate t is q->seed + t); the batch keeps the plans' addresses
+ * (destroy it before them) and holds device memory for both passes of every
+ * replicate: n x 24 search instances at the reduced lattice size and n x n_nodes
+ * node instances. Errors: INVALID, NOMEM, HIP. */
+vecchia_status vecchia_mixbatch_create(const vecchia_plan_t* plans, int32_t n, int32_t n_nodes,
+                                       const vecchia_qmc* q, vecchia_mixbatch_t* out);
+
+/* Evaluate every replicate's mixture with the rule of vecchia_mixture_logcdf
+ * (mix->n_nodes must equal the batch's): one batched search launch set, one
+ * synchronisation of hip_stream, one batched node launch set, one wave per
+ * replicate to combine. x_dev: the replicates' thresholds concatenated (plan t's
+ * D_t values in its user order, device). cov_override: NULL or one covariance
+ * for every plan (same family and nu). out_dev: n x {log G_t, se_t} (device);
+ * total_dev (may be NULL): {sum_t log G_t, sqrt(sum_t se_t^2)} (device).
+ * Replicate t's result equals vecchia_mixture_logcdf on its plan with seed
+ * q->seed + t. Errors: INVALID, NOMEM, HIP; NOT_PD through vecchia_mixbatch_status. */
+vecchia_status vecchia_mixbatch_logcdf(vecchia_mixbatch_t mb, const double* x_dev, const vecchia_mixture* mix,
+                                       const vecchia_cov* cov_override, double* out_dev, double* total_dev,
+                                       void* hip_stream);
+
+/* Wait for the last call and report, per replicate, the first plan-order term
+ * whose Cholesky failed in the node pass (-1 if none; n entries, may be NULL):
+ * OK or NOT_PD. */
+vecchia_status vecchia_mixbatch_status(vecchia_mixbatch_t mb, int64_t* bad_terms_host);
+
+/* Wait for outstanding work and free the batch. */
+vecchia_status vecchia_mixbatch_destroy(vecchia_mixbatch_t mb);
 
 /* Launch-shape autotuner (the batched launch of Section 2.2, eq. (6): terms of
  * all instances that share K run in one launch, one wave per work item of

@@ -129,14 +129,15 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
-// Scale-mixture combination (one wave, node k on lane k; fixed butterflies).
-__global__ __launch_bounds__(64) void mixture_combine(const double* __restrict__ node_out, MixWeights mw,
-                                                      double* __restrict__ out, double* __restrict__ nodes_out) {
+// Scale-mixture combination of one mixture (one wave, node k on lane k; fixed
+// butterflies): out = {log sum_k exp(logw_k + lf_k), sqrt(sum_k (c_k / G)^2 se_k^2)}.
+__device__ void combine_wave(const double* __restrict__ node_out, double logw, int n,
+                             double* __restrict__ out, double* __restrict__ nodes_out) {
   const int lane = threadIdx.x;
-  const bool on = lane < mw.n;
+  const bool on = lane < n;
   const double lf = on ? node_out[2 * lane] : 0.0;
   const double se = on ? node_out[2 * lane + 1] : 0.0;
-  const double c = on ? mw.logw[lane] + lf : -HUGE_VAL;
+  const double c = on ? logw + lf : -HUGE_VAL;
   const double mx = wave_max(on ? c : -HUGE_VAL);
   double logG;
   if (mx == -HUGE_VAL) {
@@ -157,6 +158,48 @@ __global__ __launch_bounds__(64) void mixture_combine(const double* __restrict__
   }
 }
 
+__global__ __launch_bounds__(64) void mixture_combine(const double* __restrict__ node_out, MixWeights mw,
+                                                      double* __restrict__ out, double* __restrict__ nodes_out) {
+  const int lane = threadIdx.x;
+  combine_wave(node_out, lane < mw.n ? mw.logw[lane] : 0.0, mw.n, out, nodes_out);
+}
+
+// Many mixtures (one wave each): mixture t's n nodes at node_out + 2 n t, its log
+// weights at logw + n t, its result at out + 2 t.
+__global__ __launch_bounds__(64) void mixture_combine_many(const double* __restrict__ node_out,
+                                                           const double* __restrict__ logw, int n,
+                                                           double* __restrict__ out) {
+  const int64_t t = blockIdx.x;
+  const int lane = threadIdx.x;
+  combine_wave(node_out + 2 * n * t, lane < n ? logw[n * t + lane] : 0.0, n, out + 2 * t, nullptr);
+}
+
+// Sum over mixtures in a fixed order: total = {sum_t log G_t, sqrt(sum_t se_t^2)}.
+__global__ __launch_bounds__(kFinalizeThreads) void mixture_total(const double* __restrict__ out, int64_t n,
+                                                                   double* __restrict__ total) {
+  __shared__ double red_lg[kFinalizeThreads];
+  __shared__ double red_se[kFinalizeThreads];
+  double lg = 0.0, se = 0.0;
+  for (int64_t t = threadIdx.x; t < n; t += kFinalizeThreads) {
+    lg += out[2 * t];
+    se += out[2 * t + 1] * out[2 * t + 1];
+  }
+  red_lg[threadIdx.x] = lg;
+  red_se[threadIdx.x] = se;
+  __syncthreads();
+  for (int o = kFinalizeThreads / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      red_lg[threadIdx.x] += red_lg[threadIdx.x + o];
+      red_se[threadIdx.x] += red_se[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    total[0] = red_lg[0];
+    total[1] = sqrt(red_se[0]);
+  }
+}
+
 }  // namespace
 
 hipError_t launch_mixture_combine(const double* node_out, const MixWeights& mw, double* out, double* nodes_out,
@@ -164,6 +207,18 @@ hipError_t launch_mixture_combine(const double* node_out, const MixWeights& mw, 
   if (mw.n < 1 || mw.n > kMaxMixNodes) return hipErrorInvalidValue;
   hipLaunchKernelGGL(mixture_combine, dim3(1), dim3(64), 0, s, node_out, mw, out, nodes_out);
   return hipGetLastError();
+}
+
+hipError_t launch_mixture_combine_many(const double* node_out, const double* logw, int n_nodes, int64_t n_mix,
+                                       double* out, double* total, hipStream_t s) {
+  if (n_nodes < 1 || n_nodes > kMaxMixNodes || n_mix < 1 || n_mix > 0x7fffffffLL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(mixture_combine_many, dim3((unsigned)n_mix), dim3(64), 0, s, node_out, logw, n_nodes, out);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess && total) {
+    hipLaunchKernelGGL(mixture_total, dim3(1), dim3(kFinalizeThreads), 0, s, out, n_mix, total);
+    e = hipGetLastError();
+  }
+  return e;
 }
 
 hipError_t launch_finalize(const InstDesc* d_insts, int n_inst, const int64_t* d_term_bases,

@@ -147,6 +147,38 @@ vecchia_status ensure_batch(vecchia_plan_s* P, std::unique_ptr<Batch>* slot, int
 }  // namespace
 }  // namespace vecchia
 
+// Scale mixtures of many plans evaluated together (the censored likelihood of
+// Section 4 sums log G_{I_t}(x_t) over replicates t): both passes of every
+// replicate run as one batch each.
+struct vecchia_mixbatch_s {
+  std::vector<vecchia_plan_s*> plans;
+  int n_nodes = 0;
+  vecchia_qmc q{};
+  int device = 0;
+  std::unique_ptr<vecchia::Batch> search, nodes;
+  double* d_search = nullptr;   // n x 24 x {log h, se}
+  double* d_nodes = nullptr;    // n x n_nodes x {log h, se}
+  double* d_logw = nullptr;     // n x n_nodes
+  double* h_search = nullptr;   // pinned copy of d_search
+  double* h_logw = nullptr;     // pinned staging of d_logw
+  hipEvent_t logw_ev = nullptr; // the last upload of h_logw
+  bool logw_used = false;
+  std::vector<double> scales1, scales2;
+  std::vector<uint64_t> seeds1, seeds2;
+};
+
+namespace {
+void free_mixbatch(vecchia_mixbatch_s* m) {
+  hipFree(m->d_search);
+  hipFree(m->d_nodes);
+  hipFree(m->d_logw);
+  if (m->h_search) hipHostFree(m->h_search);
+  if (m->h_logw) hipHostFree(m->h_logw);
+  if (m->logw_ev) hipEventDestroy(m->logw_ev);
+  delete m;
+}
+}  // namespace
+
 extern "C" {
 
 vecchia_status vecchia_mixture_search(const vecchia_mixture* mix, double* scales_out) {
@@ -225,6 +257,143 @@ vecchia_status vecchia_mixture_logcdf(vecchia_plan_t plan, const double* x_dev, 
   if (st != VECCHIA_OK) return st;
   e = launch_mixture_combine(node_out, mw, out_dev, nodes_dev, s);
   if (e != hipSuccess) return hip_error(e, "mixture combination");
+  return VECCHIA_OK;
+}
+
+vecchia_status vecchia_mixbatch_create(const vecchia_plan_t* plans, int32_t n, int32_t n_nodes,
+                                       const vecchia_qmc* q, vecchia_mixbatch_t* out) {
+  using namespace vecchia;
+  if (!plans || !q || !out || n < 1) return set_error(VECCHIA_E_INVALID, "bad mixture batch arguments");
+  *out = nullptr;
+  if (n_nodes < 1 || n_nodes > kMaxMixNodes) return set_error(VECCHIA_E_INVALID, "n_nodes must be in 1..64");
+  std::string why;
+  if (!valid_qmc(*q, &why)) return set_error(VECCHIA_E_INVALID, why);
+  if ((int64_t)n * std::max(kMixSearch, n_nodes) > 0x7fffffffLL)
+    return set_error(VECCHIA_E_INVALID, "too many plans");
+  std::unique_ptr<vecchia_mixbatch_s, void (*)(vecchia_mixbatch_s*)> m(new (std::nothrow) vecchia_mixbatch_s(),
+                                                                        free_mixbatch);
+  if (!m) return set_error(VECCHIA_E_NOMEM, "host allocation");
+  m->plans.assign(plans, plans + n);
+  for (auto* P : m->plans)
+    if (!P) return set_error(VECCHIA_E_INVALID, "null plan in mixture batch");
+  m->n_nodes = n_nodes;
+  m->q = *q;
+  hipGetDevice(&m->device);
+  vecchia_qmc qs = *q;
+  qs.n_points = search_points(q->n_points);
+  std::vector<vecchia_plan_s*> p1, p2;
+  std::vector<vecchia_qmc> q1, q2;
+  std::vector<int64_t> off1, off2;
+  int64_t xo = 0;
+  for (int t = 0; t < n; ++t) {
+    for (int k = 0; k < kMixSearch; ++k) {
+      p1.push_back(m->plans[t]);
+      q1.push_back(qs);
+      off1.push_back(xo);
+      m->seeds1.push_back(q->seed + (uint64_t)t);
+    }
+    for (int k = 0; k < n_nodes; ++k) {
+      p2.push_back(m->plans[t]);
+      q2.push_back(*q);
+      off2.push_back(xo);
+      m->seeds2.push_back(q->seed + (uint64_t)t);
+    }
+    xo += m->plans[t]->D;
+  }
+  vecchia_status st = Batch::create(p1, q1, &m->search);
+  if (st == VECCHIA_OK) st = Batch::create(p2, q2, &m->nodes);
+  if (st != VECCHIA_OK) return st;
+  m->search->set_x_offsets(off1);
+  m->nodes->set_x_offsets(off2);
+  m->scales1.resize(p1.size());
+  m->scales2.resize(p2.size());
+  const size_t n1 = (size_t)n * kMixSearch, n2 = (size_t)n * n_nodes;
+  hipError_t e = hipMalloc(&m->d_search, sizeof(double) * 2 * n1);
+  if (e == hipSuccess) e = hipMalloc(&m->d_nodes, sizeof(double) * 2 * n2);
+  if (e == hipSuccess) e = hipMalloc(&m->d_logw, sizeof(double) * n2);
+  if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&m->h_search), sizeof(double) * 2 * n1);
+  if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&m->h_logw), sizeof(double) * n2);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&m->logw_ev, hipEventDisableTiming);
+  if (e != hipSuccess) return hip_error(e, "mixture batch buffers");
+  *out = m.release();
+  return VECCHIA_OK;
+}
+
+vecchia_status vecchia_mixbatch_logcdf(vecchia_mixbatch_t mb, const double* x_dev, const vecchia_mixture* mix,
+                                       const vecchia_cov* cov_override, double* out_dev, double* total_dev,
+                                       void* hip_stream) {
+  using namespace vecchia;
+  if (!mb || !x_dev || !out_dev) return set_error(VECCHIA_E_INVALID, "null pointer");
+  std::string why;
+  if (!valid_mixture(mix, &why)) return set_error(VECCHIA_E_INVALID, why);
+  if (mix->n_nodes != mb->n_nodes) return set_error(VECCHIA_E_INVALID, "n_nodes differs from the batch's");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  const int n = (int)mb->plans.size();
+  const int nn = mb->n_nodes;
+  std::vector<vecchia_cov> covs;
+  if (cov_override) covs.assign(std::max(mb->scales1.size(), mb->scales2.size()), *cov_override);
+  // pass 1: the search of every replicate
+  for (int t = 0; t < n; ++t)
+    for (int k = 0; k < kMixSearch; ++k)
+      mb->scales1[(size_t)t * kMixSearch + k] = mixture_scale(search_v(k), mix->beta, mix->gamma);
+  vecchia_status st = mb->search->run(x_dev, mb->scales1.data(), cov_override ? covs.data() : nullptr,
+                                      mb->d_search, nullptr, mb->seeds1.data(), s);
+  if (st != VECCHIA_OK) return st;
+  const size_t n1 = (size_t)n * kMixSearch;
+  hipError_t e = hipMemcpyAsync(mb->h_search, mb->d_search, sizeof(double) * 2 * n1, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_error(e, "mixture batch search pass");
+  // the rule of every replicate, once the previous call's weight upload (maybe
+  // on another stream) has read the staging buffer
+  if (mb->logw_used) e = hipEventSynchronize(mb->logw_ev);
+  if (e != hipSuccess) return hip_error(e, "mixture batch staging wait");
+  for (int t = 0; t < n; ++t) {
+    double logh[kMixSearch];
+    for (int k = 0; k < kMixSearch; ++k) logh[k] = mb->h_search[2 * ((size_t)t * kMixSearch + k)];
+    double lo, hi;
+    window_for(logh, &lo, &hi);
+    if (std::isnan(lo)) lo = 0.0, hi = kVMax;
+    double v[kMaxMixNodes];
+    rule_for(*mix, lo, hi, v, mb->scales2.data() + (size_t)t * nn, mb->h_logw + (size_t)t * nn);
+  }
+  e = hipMemcpyAsync(mb->d_logw, mb->h_logw, sizeof(double) * (size_t)n * nn, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipEventRecord(mb->logw_ev, s);
+  if (e != hipSuccess) return hip_error(e, "mixture batch weights");
+  mb->logw_used = true;
+  // pass 2: Gauss-Legendre nodes of every replicate, then one wave per replicate
+  st = mb->nodes->run(x_dev, mb->scales2.data(), cov_override ? covs.data() : nullptr, mb->d_nodes, nullptr,
+                      mb->seeds2.data(), s);
+  if (st != VECCHIA_OK) return st;
+  e = launch_mixture_combine_many(mb->d_nodes, mb->d_logw, nn, n, out_dev, total_dev, s);
+  if (e != hipSuccess) return hip_error(e, "mixture batch combination");
+  return VECCHIA_OK;
+}
+
+vecchia_status vecchia_mixbatch_status(vecchia_mixbatch_t mb, int64_t* bad_terms_host) {
+  using namespace vecchia;
+  if (!mb) return set_error(VECCHIA_E_INVALID, "null mixture batch");
+  std::vector<int64_t> bad;
+  vecchia_status st = mb->nodes->status(&bad);
+  if (bad_terms_host) {
+    const int n = (int)mb->plans.size();
+    for (int t = 0; t < n; ++t) {
+      int64_t b = -1;
+      for (int k = 0; k < mb->n_nodes; ++k) {
+        const int64_t v = bad[(size_t)t * mb->n_nodes + k];
+        if (v >= 0 && (b < 0 || v < b)) b = v;
+      }
+      bad_terms_host[t] = b;
+    }
+  }
+  return st;
+}
+
+vecchia_status vecchia_mixbatch_destroy(vecchia_mixbatch_t mb) {
+  using namespace vecchia;
+  if (!mb) return set_error(VECCHIA_E_INVALID, "null mixture batch");
+  if (mb->nodes && mb->nodes->last_stream() != nullptr) hipStreamSynchronize(mb->nodes->last_stream());
+  hipDeviceSynchronize();
+  free_mixbatch(mb);
   return VECCHIA_OK;
 }
 

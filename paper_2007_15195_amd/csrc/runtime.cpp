@@ -436,7 +436,7 @@ vecchia_status Batch::run(const double* x_dev, const double* scales, const vecch
     }
     const double sc = scales ? scales[j] : 1.0;
     if (!(std::isfinite(sc) && sc > 0)) return set_error(VECCHIA_E_INVALID, "scale must be finite and > 0");
-    d[j].x = shared_x_ ? x_dev : x_dev + xo;
+    d[j].x = !x_off_.empty() ? x_dev + x_off_[j] : shared_x_ ? x_dev : x_dev + xo;
     d[j].out = out_dev + 2 * j;
     d[j].terms_out = terms_dev;
     d[j].inv_scale = 1.0 / sc;

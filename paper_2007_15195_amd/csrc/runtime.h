@@ -58,6 +58,9 @@ class Batch {
   // consecutive slices of x_dev: several instances of one plan at different
   // scales, as the scale-mixture quadrature needs.
   void set_shared_x(bool on) { shared_x_ = on; }
+  // Instance j reads its thresholds at x_dev + off[j] (n() offsets): several
+  // instances of each of several plans, as the batched scale mixture needs.
+  void set_x_offsets(std::vector<int64_t> off) { x_off_ = std::move(off); }
   // After a completed run(): re-launches the launch with the most work `reps`
   // times on s between HIP events and returns the median duration (autotuner).
   vecchia_status time_main_launch(hipStream_t s, int reps, float* median_ms);
@@ -121,6 +124,7 @@ class Batch {
   InstDesc* ext_stage_ = nullptr;
   bool tables_uploaded_ = false;
   bool shared_x_ = false;
+  std::vector<int64_t> x_off_;
 
   hipGraphExec_t graph_exec_ = nullptr;
   hipStream_t graph_stream_ = nullptr;

@@ -98,6 +98,11 @@ struct MixWeights {
 // from node_out (n x {log F_k, se_k}); nodes_out (optional) receives a copy of node_out.
 hipError_t launch_mixture_combine(const double* node_out, const MixWeights& mw, double* out, double* nodes_out,
                                   hipStream_t s);
+// n_mix mixtures of n_nodes nodes each (node_out: n_mix x n_nodes x {log F, se};
+// logw: n_mix x n_nodes); out: n_mix x {log G, se}; total (optional): the sum of
+// the log G and the root sum of squares of the SEs.
+hipError_t launch_mixture_combine_many(const double* node_out, const double* logw, int n_nodes, int64_t n_mix,
+                                       double* out, double* total, hipStream_t s);
 hipError_t launch_finalize(const InstDesc* d_insts, int n_inst, const int64_t* d_term_bases,
                            int64_t total_terms, const Aux64* aux64, const double* sums,
                            double2* term_res, hipStream_t s);

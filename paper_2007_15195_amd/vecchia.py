@@ -34,6 +34,7 @@ EXPORTED = [
     "vecchia_autotune", "vecchia_tuning_get", "vecchia_tuning_set", "vecchia_calibrate_valu",
     "vecchia_mixture_logcdf", "vecchia_mixture_rule", "vecchia_mixture_search",
     "vecchia_plan_censored", "vecchia_plan_from_cov_censored", "vecchia_plan_censoring",
+    "vecchia_mixbatch_create", "vecchia_mixbatch_logcdf", "vecchia_mixbatch_status", "vecchia_mixbatch_destroy",
 ]
 
 
@@ -79,6 +80,11 @@ def lib():
         "vecchia_plan_from_cov_censored": [c_void_p, c_int64, c_void_p, c_int32, c_int64, c_void_p,
                                            POINTER(c_void_p)],
         "vecchia_plan_censoring": [c_void_p, POINTER(c_int64)],
+        "vecchia_mixbatch_create": [c_void_p, c_int32, c_int32, POINTER(vecchia_qmc), POINTER(c_void_p)],
+        "vecchia_mixbatch_logcdf": [c_void_p, c_void_p, POINTER(vecchia_mixture), c_void_p, c_void_p, c_void_p,
+                                    c_void_p],
+        "vecchia_mixbatch_status": [c_void_p, c_void_p],
+        "vecchia_mixbatch_destroy": [c_void_p],
         "vecchia_replan": [c_void_p, c_void_p, c_int32, c_void_p, c_void_p],
         "vecchia_plan_info": [c_void_p, POINTER(c_int64), POINTER(c_int32)],
         "vecchia_plan_neighbours": [c_void_p, c_void_p, c_void_p],
@@ -432,3 +438,33 @@ def vecchia_mixture_logcdf(plan: int, x, mix: vecchia_mixture, qmc, out, nodes=N
                                         _dev_ptr(out, 2, "out"),
                                         None if nodes is None else _dev_ptr(nodes, 2 * int(mix.n_nodes), "nodes"),
                                         _stream_ptr(stream)))
+
+
+def vecchia_mixbatch_create(plans, n_nodes: int, qmc) -> int:
+    n = len(plans)
+    arr = (c_void_p * n)(*plans)
+    q = as_qmc(qmc)
+    h = c_void_p()
+    _check(lib().vecchia_mixbatch_create(ctypes.addressof(arr), n, int(n_nodes), byref(q), byref(h)))
+    return h.value
+
+
+def vecchia_mixbatch_logcdf(mb: int, x, mix: vecchia_mixture, out, total=None, cov_override=None,
+                            stream=None) -> None:
+    c = as_cov(cov_override)
+    _check(lib().vecchia_mixbatch_logcdf(mb, _dev_ptr(x, None, "x"), byref(mix),
+                                         None if c is None else ctypes.addressof(c), _dev_ptr(out, None, "out"),
+                                         None if total is None else _dev_ptr(total, 2, "total"),
+                                         _stream_ptr(stream)))
+
+
+def vecchia_mixbatch_status(mb: int, n: int):
+    bad = np.empty(n, dtype=np.int64)
+    st = lib().vecchia_mixbatch_status(mb, bad.ctypes.data)
+    if st not in (VECCHIA_OK, 3):
+        _check(st)
+    return bad
+
+
+def vecchia_mixbatch_destroy(mb: int) -> None:
+    _check(lib().vecchia_mixbatch_destroy(mb))

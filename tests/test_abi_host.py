@@ -190,3 +190,20 @@ def test_censored_matrix_plan_host_setup_runs_before_device_work():
         pytest.skip("a device is present: the GPU tests build these plans")
     with pytest.raises(V.VecchiaError):
         V.vecchia_plan_from_cov_censored(np.eye(4), 3, 2, nbr=[[], [0], [0, 1], [1, 2]], stream=0)
+
+
+def test_mixture_batch_arguments_rejected_on_the_host():
+    q = V.make_qmc(1024, 4, 1, V.VECCHIA_FP64)
+    with pytest.raises(V.VecchiaError) as e:
+        V.vecchia_mixbatch_create([], 16, q)
+    assert e.value.status == 1
+    for n_nodes in (0, 65):
+        with pytest.raises(V.VecchiaError):
+            V.vecchia_mixbatch_create([None], n_nodes, q)
+    with pytest.raises(V.VecchiaError):
+        V.vecchia_mixbatch_create([None], 16, V.make_qmc(0, 4, 1, V.VECCHIA_FP64))
+    with pytest.raises(V.VecchiaError):
+        V.vecchia_mixbatch_create([None], 16, q)                                 # null plan
+    with pytest.raises(V.VecchiaError):
+        V.vecchia_mixbatch_destroy(None)
+

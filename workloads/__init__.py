@@ -254,3 +254,37 @@ def censored_replicate(D: int, m: int, seed: int, frac_obs: float = 0.05, orderi
     inst = Instance(f"censored_D{D}_m{m}_s{seed}", locs, x, m, ordering, Cov(family, nu, 1.0, rho, nugget),
                     QMC(n_points, n_shifts, seed + 7, precision))
     return CensoredReplicate(inst, obs)
+
+
+def station_network(n: int = 528, seed: int = seed_for(6, 0)) -> np.ndarray:
+    """n irregular station locations in a 29 x 12 box (degrees of longitude and
+    latitude of a western/central European network; the paper's 528 stations
+    are not used)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return np.stack([rng.uniform(-5.0, 24.0, n), rng.uniform(43.0, 55.0, n)], axis=1)
+
+
+def network_replicates(T: int = 1006, n: int = 528, missing: float = 0.326, exceed: float = 0.05,
+                       rho: float = 1.31, m: int = 10, n_points: int = 1000, n_shifts: int = 10,
+                       precision: int = PREC_FP32, seed: int = seed_for(6, 1)):
+    """T weekly replicates on station_network(n), shaped like the application of
+    Section 4.1: each station missing with probability `missing` in a week
+    (dropped from that replicate), one smooth-field draw per week (exponential
+    correlation scale rho), censored at each station's empirical (1 - exceed)
+    quantile over the T weeks. Returns (locs, [CensoredReplicate]); replicate t's
+    Instance holds its present stations only (locations in the same units)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    locs = station_network(n)
+    fields = np.stack([smooth_field(locs, rng, 0.5, rho, n_features=256) for _ in range(T)])
+    u = np.quantile(fields, 1.0 - exceed, axis=0)
+    present = rng.random((T, n)) >= missing
+    reps = []
+    for t in range(T):
+        idx = np.flatnonzero(present[t])
+        X = fields[t, idx]
+        obs = X > u[idx]
+        x = np.where(obs, X, u[idx])
+        inst = Instance(f"network_week{t}", locs[idx], x, m, ORDER_MAXMIN, Cov(COV_EXPONENTIAL, 0.5, 1.0, rho, 0.0),
+                        QMC(n_points, n_shifts, seed_for(6, 2), precision))
+        reps.append(CensoredReplicate(inst, obs))
+    return locs, reps
