@@ -1,6 +1,6 @@
 """Benchmark of the Vecchia log-CDF hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--sections c1,c2,c3,c4,c5,mix]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--sections c1,c2,c3,c4,c5,mix,cens]
 
 Headline workload (the JSON line's value): D = 2,500 locations uniform in
 [0,1]^2, Matern nu = 3/2 (range 0.1, nugget 1e-8), maxmin ordering, m = 10,
@@ -28,7 +28,12 @@ baseline on a bounded sample, and one object per further workload:
               loop: capacity with every request queued at once, then Poisson
               arrivals at 80 % of it with p50/p99 latency;
   scale_mixture  the scale-mixture CDF E Phi_D(x / R), R Pareto(2), on the headline
-              geometry (34 evaluations per call: 2 first-pass + 32 nodes).
+              geometry (24 search evaluations at 1/16 size + 48 nodes per call);
+  censored_likelihood  the censored log-likelihood of Section 4 over 1006 weekly
+              replicates on 528 stations (about 356 present, 18 censored-above
+              per week), anisotropic exponential model at Table 1's values,
+              m = 10, 1000 x 10 points, 48 nodes per replicate, in one
+              mixture batch; FP64 on 128 replicates for the comparison.
 The launch shape of each workload is set by vecchia_autotune beforehand.
 """
 from __future__ import annotations
@@ -73,7 +78,8 @@ def parse():
     ap.add_argument("--cpu-terms", type=int, default=500)
     ap.add_argument("--fp32-only", action="store_true",
                     help="time the full FP32 step only (short runs under a profiler)")
-    ap.add_argument("--sections", default="c1,c2,c3,c4,c5,mix",
+    ap.add_argument("--censored-T", type=int, default=1006)
+    ap.add_argument("--sections", default="c1,c2,c3,c4,c5,mix,cens",
                     help="comma list of workloads to run besides the headline (c2 is always run)")
     ap.add_argument("--serving-requests", type=int, default=200)
     ap.add_argument("--no-autotune", action="store_true")
@@ -151,7 +157,8 @@ def bench_c1(V, torch, args):
 
 def bench_mixture(V, torch, args):
     """Scale-mixture CDF G(x) = E Phi_D(x / R), R Pareto(gamma = 2) (eqs. (8)-(9)),
-    on the headline geometry: 32 Gauss-Laguerre nodes + 2 first-pass scales."""
+    on the headline geometry: 24 search evaluations at 1/16 of the lattice size,
+    then 48 Gauss-Legendre nodes."""
     import workloads as W
     inst = W.uniform2500_matern15()
     stream = torch.cuda.Stream()
@@ -159,9 +166,13 @@ def bench_mixture(V, torch, args):
     plan = V.vecchia_plan(inst.locs, inst.ordering, inst.m, inst.cov, stream=sp)
     x = torch.tensor(inst.x, dtype=torch.float64, device="cuda")
     out = torch.empty(2, dtype=torch.float64, device="cuda")
-    mix = V.make_mixture(0.0, 2.0, 32)
-    res = {"workload": inst.name + "_pareto2_mixture", "beta": 0.0, "gamma": 2.0, "n_nodes": 32,
-           "evaluations_per_call": 34}
+    n_nodes = 48
+    mix = V.make_mixture(0.0, 2.0, n_nodes)
+    n_search = max(64, ((inst.qmc.n_points // 16 + 63) // 64) * 64)
+    full_equiv = n_nodes + V.MIX_SEARCH_NODES * n_search / inst.qmc.n_points
+    res = {"workload": inst.name + "_pareto2_mixture", "beta": 0.0, "gamma": 2.0, "n_nodes": n_nodes,
+           "search_evaluations": V.MIX_SEARCH_NODES, "search_n_points": n_search,
+           "full_size_evaluations_per_call": full_equiv}
     got = {}
     for name, prec, reps in (("fp32", V.VECCHIA_FP32_LOOP, 5), ("fp64", V.VECCHIA_FP64, 1)):
         q = V.make_qmc(inst.qmc.n_points, inst.qmc.n_shifts, inst.qmc.seed, prec)
@@ -169,11 +180,98 @@ def bench_mixture(V, torch, args):
         o = out.cpu().numpy()
         got[name] = o
         res[name] = {"ms_per_call": 1e3 * sec, "calls_per_s": 1.0 / sec,
-                     "terms_per_s": 34 * inst.D / sec, "logG": float(o[0]), "se": float(o[1])}
+                     "terms_per_s": full_equiv * inst.D / sec, "logG": float(o[0]), "se": float(o[1])}
     res["fp32_speedup"] = res["fp64"]["ms_per_call"] / res["fp32"]["ms_per_call"]
     res["fp32_vs_fp64_rel"] = abs(got["fp32"][0] - got["fp64"][0]) / abs(got["fp64"][0])
     V.vecchia_plan_destroy(plan)
     return res
+
+
+# Section 4.1 / Table 1: range, rotation angle, aspect ratio and mixing law
+# of the application's fitted model (gamma fixed at 1).
+APP_RHO, APP_PHI, APP_ASPECT, APP_BETA, APP_GAMMA = 1.31, 1.10, 2.29, 0.82, 1.0
+
+
+def bench_censored(V, torch, args):
+    """Censored log-likelihood sum_t log G_{I_t}(x_t) (Section 4, eqs. (9), (11))
+    over T = 1006 weekly replicates on 528 stations (about 356 present and 18
+    above the censoring level per week), anisotropic exponential covariance
+    through the coordinate map, m = 10, 1000 x 10 lattice points, 48 nodes per
+    replicate, all replicates in one mixture batch; FP64 on the first 128
+    replicates for the precision comparison."""
+    import workloads as W
+    _, reps = W.network_replicates(T=args.censored_T, n_points=1000, n_shifts=10)
+    T = len(reps)
+    stream = torch.cuda.Stream()
+    sp = stream.cuda_stream
+    cov = V.make_cov(V.VECCHIA_COV_EXPONENTIAL, 0.5, 1.0, APP_RHO, 0.0)
+    t0 = time.perf_counter()
+    plans = []
+    for r in reps:
+        mapped = V.vecchia_map_anisotropic(r.inst.locs, APP_PHI, APP_ASPECT)
+        plans.append(V.vecchia_plan_censored(mapped, r.observed, V.VECCHIA_ORDER_MAXMIN, 10, cov, stream=sp))
+    t_plans = time.perf_counter() - t0
+    D = np.array([r.inst.D for r in reps])
+    n_obs = np.array([int(r.observed.sum()) for r in reps])
+    n_nodes = 48
+    mix = V.make_mixture(APP_BETA, APP_GAMMA, n_nodes)
+    n_search = max(64, ((1000 // 16 + 63) // 64) * 64)
+    res = {"workload": f"network528_T{T}_censored_m10", "replicates": T, "mean_D": float(D.mean()),
+           "mean_observed": float(n_obs.mean()), "n_points": 1000, "n_shifts": 10, "n_nodes": n_nodes,
+           "search_n_points": n_search, "beta": APP_BETA, "gamma": APP_GAMMA, "plan_seconds": t_plans}
+    got = {}
+    for name, prec, nrep, reps_t in (("fp32", V.VECCHIA_FP32_LOOP, T, 2), ("fp64", V.VECCHIA_FP64, min(T, 128), 1),
+                                     ("fp32_subset", V.VECCHIA_FP32_LOOP, min(T, 128), 2)):
+        q = V.make_qmc(1000, 10, 2024, prec)
+        mb = V.vecchia_mixbatch_create(plans[:nrep], n_nodes, q)
+        x = torch.tensor(np.concatenate([r.inst.x for r in reps[:nrep]]), dtype=torch.float64, device="cuda")
+        out = torch.empty((nrep, 2), dtype=torch.float64, device="cuda")
+        total = torch.empty(2, dtype=torch.float64, device="cuda")
+        sec = _timed(torch, lambda: V.vecchia_mixbatch_logcdf(mb, x, mix, out, total=total, stream=sp), reps_t)
+        o = out.cpu().numpy()
+        tot = total.cpu().numpy()
+        got[name] = o
+        terms = float(D[:nrep].sum()) * (n_nodes + V.MIX_SEARCH_NODES * n_search / 1000)
+        res[name] = {"replicates": nrep, "seconds_per_likelihood": sec, "replicates_per_s": nrep / sec,
+                     "full_size_terms_per_s": terms / sec, "loglik": float(tot[0]), "se": float(tot[1])}
+        V.vecchia_mixbatch_destroy(mb)
+    res["fp32_speedup_on_subset"] = res["fp64"]["seconds_per_likelihood"] / res["fp32_subset"]["seconds_per_likelihood"]
+    d = np.abs(got["fp32_subset"][:, 0] - got["fp64"][:, 0])
+    res["fp32_vs_fp64"] = {"max_abs_replicate": float(d.max()),
+                           "rel_total": abs(got["fp32_subset"][:, 0].sum() - got["fp64"][:, 0].sum())
+                           / abs(got["fp64"][:, 0].sum())}
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline_censored(reps, n_nodes, 2024)
+    for p in plans:
+        V.vecchia_plan_destroy(p)
+    return res
+
+
+def cpu_baseline_censored(reps, n_nodes, seed):
+    """The oracle on one replicate (the first with the median number of present
+    sites): its full mixture rule over the censored Vecchia terms."""
+    import oracle
+    from oracle import censored as CZ
+    from oracle import mixture as M
+    import workloads as W
+    D = np.array([r.inst.D for r in reps])
+    t = int(np.flatnonzero(D == int(np.median(D)))[0]) if np.any(D == int(np.median(D))) else 0
+    r = reps[t]
+    procs = oracle.vecchia.default_processes()
+    mapped = oracle.covariance.anisotropic_coords(r.inst.locs, APP_PHI, APP_ASPECT)
+    t0 = time.perf_counter()
+    pc = CZ.censored_plan(mapped, r.observed, W.ORDER_MAXMIN, 10)
+
+    def ev(scale, n):
+        d = CZ.loglik(mapped, r.inst.x, r.observed, 10, W.COV_EXPONENTIAL, 0.5, 1.0, APP_RHO, 0.0, W.ORDER_MAXMIN,
+                      n, 10, seed + t, scale=scale, plan_cache=pc, processes=procs)
+        return d["logL"], d["se"]
+    ns = M.search_n_points(1000)
+    M.logcdf_mixture(lambda sc: ev(sc, 1000), APP_BETA, APP_GAMMA, n_nodes, eval_search=lambda sc: ev(sc, ns))
+    sec = time.perf_counter() - t0
+    return {"value": 1.0 / sec, "unit": "replicates/s", "cores": procs, "kind": "oracle",
+            "sample": f"replicate {t} (D = {r.inst.D}, {int(r.observed.sum())} observed): plan, 24 search and "
+                      f"{n_nodes} node evaluations ({sec:.1f} s on {procs} processes)"}
 
 
 def bench_c3(V, torch, args):
@@ -446,6 +544,8 @@ def main():
         res["c5_serving"] = bench_c5(V, torch, args)
     if "mix" in sections:
         res["scale_mixture"] = bench_mixture(V, torch, args)
+    if "cens" in sections:
+        res["censored_likelihood"] = bench_censored(V, torch, args)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(inst, args.cpu_terms)
     print(json.dumps(res), flush=True)

@@ -112,6 +112,16 @@ const char* vecchia_last_error(void);
 vecchia_status vecchia_order(const double* locs_host, int64_t D, int32_t ordering,
                              const int64_t* perm_in_host, int64_t* perm_out_host);
 
+/* Anisotropic distance of Section 4.1 as a change of coordinates (host only):
+ * h_ij = |(s_i - s_j)^T R(phi)^-1 diag(1, A)| with R(phi) the rotation by phi is
+ * the Euclidean distance between the mapped points
+ *   s' = (x cos phi - y sin phi, A (x sin phi + y cos phi)),
+ * so a plan over out_host (D x 2) with an isotropic covariance of range rho is
+ * the anisotropic model, its neighbours the nearest under h. locs_host and
+ * out_host may be the same array. Errors: INVALID (null, non-finite phi, A <= 0). */
+vecchia_status vecchia_map_anisotropic(const double* locs_host, int64_t D, double phi, double A,
+                                       double* out_host);
+
 /* Build a plan: order the D locations, copy them to the device and find, with
  * the GPU kernel knn_preceding, each component's min(m, i) nearest preceding
  * neighbours under the (squared distance, plan index) order (Section 2.1).

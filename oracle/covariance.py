@@ -38,3 +38,21 @@ def cov_matrix(pts: np.ndarray, family: int, nu: float, sigma2: float, rho: floa
     C = kernel(h, family, nu, sigma2, rho)
     C[np.diag_indices_from(C)] += nugget
     return C
+
+
+def mahalanobis_distance(si, sj, phi: float, A: float) -> float:
+    """Section 4.1's anisotropic distance: h = |Omega| with the row vector
+    Omega = (s_i - s_j)^T R(phi)^-1 diag(1, A), R(phi) the rotation by phi
+    (angle in [0, pi), aspect ratio A > 1). The exponential covariance
+    exp(-h / rho) of that section uses it."""
+    R = np.array([[math.cos(phi), -math.sin(phi)], [math.sin(phi), math.cos(phi)]])
+    d = np.asarray(si, dtype=np.float64) - np.asarray(sj, dtype=np.float64)
+    omega = d @ np.linalg.inv(R) @ np.diag([1.0, A])
+    return float(math.sqrt(omega @ omega))
+
+
+def anisotropic_coords(locs, phi: float, A: float) -> np.ndarray:
+    """Points whose Euclidean distances are mahalanobis_distance: each row
+    s^T R(phi)^-1 diag(1, A) (the map is linear, so differences map to Omega)."""
+    R = np.array([[math.cos(phi), -math.sin(phi)], [math.sin(phi), math.cos(phi)]])
+    return np.asarray(locs, dtype=np.float64) @ np.linalg.inv(R) @ np.diag([1.0, A])

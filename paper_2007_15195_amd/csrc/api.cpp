@@ -493,4 +493,19 @@ vecchia_status vecchia_batch_destroy(vecchia_batch_t batch) {
   return VECCHIA_OK;
 }
 
+vecchia_status vecchia_map_anisotropic(const double* locs_host, int64_t D, double phi, double A,
+                                       double* out_host) {
+  if (!locs_host || !out_host) return set_error(VECCHIA_E_INVALID, "null pointer");
+  if (D < 0) return set_error(VECCHIA_E_INVALID, "D must be >= 0");
+  if (!std::isfinite(phi) || !(std::isfinite(A) && A > 0.0))
+    return set_error(VECCHIA_E_INVALID, "phi must be finite and A finite and > 0");
+  const double c = std::cos(phi), sn = std::sin(phi);
+  for (int64_t i = 0; i < D; ++i) {
+    const double x = locs_host[2 * i], y = locs_host[2 * i + 1];
+    out_host[2 * i] = c * x - sn * y;
+    out_host[2 * i + 1] = A * (sn * x + c * y);
+  }
+  return VECCHIA_OK;
+}
+
 }  // extern "C"

@@ -35,6 +35,7 @@ EXPORTED = [
     "vecchia_mixture_logcdf", "vecchia_mixture_rule", "vecchia_mixture_search",
     "vecchia_plan_censored", "vecchia_plan_from_cov_censored", "vecchia_plan_censoring",
     "vecchia_mixbatch_create", "vecchia_mixbatch_logcdf", "vecchia_mixbatch_status", "vecchia_mixbatch_destroy",
+    "vecchia_map_anisotropic",
 ]
 
 
@@ -85,6 +86,7 @@ def lib():
                                     c_void_p],
         "vecchia_mixbatch_status": [c_void_p, c_void_p],
         "vecchia_mixbatch_destroy": [c_void_p],
+        "vecchia_map_anisotropic": [c_void_p, c_int64, c_double, c_double, c_void_p],
         "vecchia_replan": [c_void_p, c_void_p, c_int32, c_void_p, c_void_p],
         "vecchia_plan_info": [c_void_p, POINTER(c_int64), POINTER(c_int32)],
         "vecchia_plan_neighbours": [c_void_p, c_void_p, c_void_p],
@@ -468,3 +470,12 @@ def vecchia_mixbatch_status(mb: int, n: int):
 
 def vecchia_mixbatch_destroy(mb: int) -> None:
     _check(lib().vecchia_mixbatch_destroy(mb))
+
+
+def vecchia_map_anisotropic(locs: np.ndarray, phi: float, A: float) -> np.ndarray:
+    """Coordinates whose Euclidean distances are Section 4.1's anisotropic distances."""
+    locs = np.ascontiguousarray(locs, dtype=np.float64)
+    out = np.empty_like(locs)
+    _check(lib().vecchia_map_anisotropic(locs.ctypes.data, locs.shape[0], float(phi), float(A), out.ctypes.data))
+    return out
+

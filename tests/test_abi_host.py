@@ -2,6 +2,7 @@
 header declares, orders locations on the host exactly as the oracle does, and
 rejects bad arguments before touching a GPU."""
 import ctypes
+import math
 import os
 import re
 
@@ -207,3 +208,39 @@ def test_mixture_batch_arguments_rejected_on_the_host():
     with pytest.raises(V.VecchiaError):
         V.vecchia_mixbatch_destroy(None)
 
+
+
+def test_anisotropic_map_gives_the_mahalanobis_distance():
+    # Section 4.1: distances between mapped points equal the oracle's |Omega|,
+    # computed from the rotation and scaling matrices as printed
+    from oracle import covariance as C
+    rng = np.random.default_rng(12)
+    pts = rng.uniform(-5.0, 24.0, (40, 2))
+    for phi, A in ((1.10, 2.29), (0.0, 1.0), (2.9, 1.5), (math.pi / 2, 3.0)):
+        mp = V.vecchia_map_anisotropic(pts, phi, A)
+        for i in range(0, 40, 3):
+            for j in range(1, 40, 5):
+                want = C.mahalanobis_distance(pts[i], pts[j], phi, A)
+                got = float(np.hypot(*(mp[i] - mp[j])))
+                assert abs(got - want) <= 1e-13 * max(1.0, want)
+    with pytest.raises(V.VecchiaError):
+        V.vecchia_map_anisotropic(pts, 1.0, 0.0)
+
+
+def test_oracle_anisotropic_coords_match_its_distance():
+    from oracle import covariance as C
+    pts = np.random.default_rng(3).uniform(-5.0, 24.0, (20, 2))
+    mp = C.anisotropic_coords(pts, 1.10, 2.29)
+    for i in range(20):
+        for j in range(i):
+            want = C.mahalanobis_distance(pts[i], pts[j], 1.10, 2.29)
+            assert abs(float(np.hypot(*(mp[i] - mp[j]))) - want) <= 1e-13 * want
+
+
+def test_mahalanobis_special_cases():
+    # no rotation: the second coordinate is stretched by A; a quarter turn: the
+    # first one is
+    from oracle import covariance as C
+    assert abs(C.mahalanobis_distance([1.0, 2.0], [0.0, 0.0], 0.0, 3.0) - math.hypot(1.0, 6.0)) < 1e-14
+    assert abs(C.mahalanobis_distance([1.0, 2.0], [0.0, 0.0], math.pi / 2, 3.0) - math.hypot(2.0, 3.0)) < 1e-14
+    assert abs(C.mahalanobis_distance([0.3, -0.4], [0.0, 0.0], 0.7, 1.0) - 0.5) < 1e-15
