@@ -30,5 +30,5 @@ which one it takes in its own header. Parity of the Vecchia approximation itself
 m < D-1 and a general covariance is unpinned (no closed form exists); the tests
 pin every component and the exact special cases instead.
 """
-from . import lattice, ordering, neighbours, covariance, sov, vecchia, mixture, censored  # noqa: F401
+from . import lattice, ordering, neighbours, covariance, sov, vecchia, mixture, censored, block  # noqa: F401
 from .vecchia import logcdf, logcdf_from_cov, plan  # noqa: F401

@@ -36,15 +36,20 @@ class NotPositiveDefinite(Exception):
 
 
 def term_sums(C: np.ndarray, b: np.ndarray, n_points: int, n_shifts: int, seed: int,
-              term: int, Z: list | None = None):
+              term: int, Z: list | None = None, split: int | None = None):
     """Return (L, num[R], den[R]): per-shift lattice means of the numerator and
-    denominator integrands of the term with covariance C and limits b."""
+    denominator integrands of the term with covariance C and limits b.
+
+    split (default n - 1): the denominator is the CDF of the first `split`
+    variables, E[prod_{a<split} e_a] (a joint block term of Section 3.2 has its
+    conditioning variables first and its group last); split = 0 gives 1."""
     n = len(b)
     try:
         L = np.linalg.cholesky(C)
     except np.linalg.LinAlgError as exc:
         raise NotPositiveDefinite(str(exc)) from exc
     k = n - 1
+    split = k if split is None else split
     Z = lattice.richtmyer_generator() if Z is None else Z
     num = np.empty(n_shifts)
     den = np.empty(n_shifts)
@@ -52,6 +57,7 @@ def term_sums(C: np.ndarray, b: np.ndarray, n_points: int, n_shifts: int, seed: 
     for r in range(n_shifts):
         e = np.full(n_points, e1)
         prod = e.copy()                    # running product e_1 ... e_{a-1}
+        head = np.ones(n_points) if split == 0 else (prod.copy() if split == 1 else None)
         ys = np.zeros((k, n_points))
         for a in range(1, n):              # 0-based variable a = 1..k
             w = lattice.points(n_points, a - 1, lattice.shift(seed, term, r, a - 1), Z)
@@ -65,20 +71,22 @@ def term_sums(C: np.ndarray, b: np.ndarray, n_points: int, n_shifts: int, seed: 
             e = np.where(alive, ndtr(acc / L[a, a]), 0.0)
             if a < k:
                 prod = prod * e
-        den[r] = np.mean(prod)
+                if a + 1 == split:
+                    head = prod.copy()
+        den[r] = np.mean(head)
         num[r] = np.mean(prod * e)
     return L, num, den
 
 
 def term_estimate(C: np.ndarray, b: np.ndarray, n_points: int, n_shifts: int, seed: int,
-                  term: int, Z: list | None = None):
-    """Return (log_term, se) of one Vecchia term."""
+                  term: int, Z: list | None = None, split: int | None = None):
+    """Return (log_term, se) of one Vecchia term (split: as term_sums)."""
     if len(b) == 1:
         if not C[0, 0] > 0.0:
             raise NotPositiveDefinite("variance <= 0")
         with np.errstate(divide="ignore"):
             return float(np.log(ndtr(b[0] / math.sqrt(C[0, 0])))), 0.0
-    _, num, den = term_sums(C, b, n_points, n_shifts, seed, term, Z)
+    _, num, den = term_sums(C, b, n_points, n_shifts, seed, term, Z, split)
     nh = np.mean(num)
     dh = np.mean(den)
     with np.errstate(divide="ignore", invalid="ignore"):
