@@ -164,6 +164,38 @@ vecchia_status vecchia_plan_censored(const double* locs_host, int64_t D, int32_t
                                      const int64_t* perm_in_host, const uint8_t* observed_host, int32_t m,
                                      const vecchia_cov* cov, void* hip_stream, vecchia_plan_t* out);
 
+/* Joint (block) conditional plan (Section 3.2). The sites are ordered as by
+ * vecchia_plan and cut into consecutive groups of p (the last one ragged). The
+ * conditioning set of a group is the union of its members' m nearest
+ * neighbours among the sites of earlier groups (in member order, each list in
+ * the (d^2, index) order, first occurrence kept), so a term has at most
+ * p (m + 1) variables. Term g is Phi(x_{C_g}, x_{G_g}) / Phi(x_{C_g}) (C_g
+ * first), estimated by one SOV chain whose denominator is the prefix of its
+ * first |C_g| factors; its shift key is g. vecchia_logcdf's per-term output
+ * then has one row per group, in group order. p = 1 gives vecchia_plan's plan.
+ * The neighbour search scans all earlier sites (no grid). Errors: as
+ * vecchia_plan, and INVALID unless 1 <= p and p (m + 1) <= 32. */
+vecchia_status vecchia_plan_block(const double* locs_host, int64_t D, int32_t dim, int32_t ordering,
+                                  const int64_t* perm_in_host, int32_t m, int32_t p, const vecchia_cov* cov,
+                                  void* hip_stream, vecchia_plan_t* out);
+
+/* The terms of a block plan (host copies): *n_terms; var_off_host (n_terms + 1
+ * offsets), vars_host (var_off_host[n_terms] plan indices: each term's
+ * conditioning set, then its group) and split_host (n_terms conditioning-set
+ * sizes) may each be NULL. Errors: INVALID (not a block plan). */
+vecchia_status vecchia_plan_block_terms(vecchia_plan_t plan, int64_t* n_terms, int32_t* var_off_host,
+                                        int32_t* vars_host, int32_t* split_host);
+
+/* Plan of explicit joint terms over a D x D covariance (host, D <= 4096):
+ * term g has the variables vars_host[var_off_host[g] .. var_off_host[g+1])
+ * (1..32 distinct indices in 0..D-1) and the value
+ * Phi(all of them) / Phi(the first split_host[g]), 0 <= split < variables.
+ * log F is the sum over the n_terms terms; used for closed-form cases.
+ * Errors: INVALID (bad sizes, matrix or term lists), NOMEM, HIP. */
+vecchia_status vecchia_plan_from_cov_block(const double* cov_host, int64_t D, const int32_t* var_off_host,
+                                           const int32_t* vars_host, const int32_t* split_host, int64_t n_terms,
+                                           void* hip_stream, vecchia_plan_t* out);
+
 /* Censored plan over an explicit covariance (as vecchia_plan_from_cov) whose
  * first n_observed variables are the observed ones (0 <= n_observed <= D).
  * Errors: as vecchia_plan_from_cov, and INVALID for n_observed outside 0..D. */
@@ -179,7 +211,7 @@ vecchia_status vecchia_plan_censoring(vecchia_plan_t plan, int64_t* n_observed);
  * knn_preceding kernel on hip_stream. Allocates nothing; the host ordering of
  * this call overlaps GPU work already queued. Must be ordered with the plan's
  * other calls on one stream. locs_host / perm_in_host as in vecchia_plan.
- * Errors: INVALID (matrix or censored plan, bad arguments), HIP. */
+ * Errors: INVALID (matrix, censored or block plan, bad arguments), HIP. */
 vecchia_status vecchia_replan(vecchia_plan_t plan, const double* locs_host, int32_t ordering,
                               const int64_t* perm_in_host, void* hip_stream);
 

@@ -38,6 +38,9 @@ void free_plan_buffers(vecchia_plan_s* P) {
   hipFree(P->d_nbr);
   hipFree(P->d_kcnt);
   hipFree(P->d_sovk);
+  hipFree(P->d_bvar_off);
+  hipFree(P->d_bvars);
+  hipFree(P->d_split);
   hipFree(P->d_mix);
   if (P->has_grid) {
     hipFree(P->grid.cell);
@@ -96,6 +99,54 @@ void set_sov_dims(vecchia_plan_s* P, const std::vector<int32_t>& nbr) {
   }
 }
 
+// Joint terms of a block plan (groups of p consecutive plan positions): the
+// conditioning set of group g is the union of its members' neighbour rows (each
+// already limited to positions before the group), in member order, first
+// occurrence kept; the term's variables are that set then the group.
+void set_block_terms(vecchia_plan_s* P, int32_t p, const std::vector<int32_t>& nbr) {
+  const int64_t D = P->D;
+  P->block = p;
+  P->n_terms = (D + p - 1) / p;
+  P->bvar_off.assign(1, 0);
+  P->bvars.clear();
+  P->split.clear();
+  P->sovk.clear();
+  P->block_nv = 0;
+  for (int64_t g0 = 0; g0 < D; g0 += p) {
+    const int64_t g1 = std::min<int64_t>(D, g0 + p);
+    std::vector<int32_t> cond;
+    for (int64_t i = g0; i < g1; ++i)
+      for (int a = 0; a < P->kcnt[i]; ++a) {
+        const int32_t j = nbr[(size_t)i * P->m + a];
+        if (std::find(cond.begin(), cond.end(), j) == cond.end()) cond.push_back(j);
+      }
+    const int nv = (int)(cond.size() + (g1 - g0));
+    for (int32_t j : cond) P->bvars.push_back(j);
+    for (int64_t i = g0; i < g1; ++i) P->bvars.push_back((int32_t)i);
+    P->bvar_off.push_back((int32_t)P->bvars.size());
+    P->split.push_back((int32_t)cond.size());
+    P->sovk.push_back(nv - 1);
+    P->block_nv = std::max(P->block_nv, nv);
+  }
+}
+
+hipError_t upload_block_terms(vecchia_plan_s* P, hipStream_t s) {
+  const int64_t T = P->n_terms;
+  hipError_t e = dev_alloc(&P->d_bvar_off, T + 1);
+  if (e == hipSuccess) e = dev_alloc(&P->d_bvars, P->bvars.size());
+  if (e == hipSuccess) e = dev_alloc(&P->d_split, T);
+  if (e == hipSuccess) e = dev_alloc(&P->d_sovk, T);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(P->d_bvar_off, P->bvar_off.data(), sizeof(int32_t) * (T + 1), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(P->d_bvars, P->bvars.data(), sizeof(int32_t) * P->bvars.size(), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(P->d_split, P->split.data(), sizeof(int32_t) * T, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(P->d_sovk, P->sovk.data(), sizeof(int32_t) * T, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  return e;
+}
+
 vecchia_status order_impl(const double* locs, int64_t D, int32_t ordering, const int64_t* perm_in,
                           int64_t* perm_out) {
   if (!locs || !perm_out) return set_error(VECCHIA_E_INVALID, "null pointer");
@@ -145,7 +196,8 @@ namespace {
 // locations, finds the neighbours on the device and records the host copies of
 // k_i and of the SOV dimension of each term.
 vecchia_status build_geometry_plan(const double* locs_host, int64_t D, std::vector<int64_t> perm, int64_t n_obs,
-                                   int32_t m, const vecchia_cov* cov, void* hip_stream, vecchia_plan_t* out) {
+                                   int32_t m, const vecchia_cov* cov, void* hip_stream, vecchia_plan_t* out,
+                                   int32_t group = 1) {
   auto* P = new (std::nothrow) vecchia_plan_s();
   if (!P) return set_error(VECCHIA_E_NOMEM, "host allocation");
   hipGetDevice(&P->device);
@@ -154,6 +206,7 @@ vecchia_status build_geometry_plan(const double* locs_host, int64_t D, std::vect
   P->cov = *cov;
   P->perm = std::move(perm);
   P->n_obs = n_obs;
+  P->n_terms = D;
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   std::vector<double> hx(D), hy(D);
   std::vector<int32_t> hp(D);
@@ -168,7 +221,7 @@ vecchia_status build_geometry_plan(const double* locs_host, int64_t D, std::vect
   if (e == hipSuccess) e = dev_alloc(&P->d_kcnt, D);
   if (e == hipSuccess && n_obs > 0) e = dev_alloc(&P->d_sovk, D);
   if (e == hipSuccess && m > 0) e = dev_alloc(&P->d_nbr, (size_t)D * m);
-  if (e == hipSuccess && m > 0 && D > kKnnGridMinD) {
+  if (e == hipSuccess && m > 0 && D > kKnnGridMinD && group == 1) {
     e = alloc_grid(P);
     grid_geometry(hx.data(), hy.data(), D, &P->grid);
   }
@@ -176,11 +229,19 @@ vecchia_status build_geometry_plan(const double* locs_host, int64_t D, std::vect
   if (e == hipSuccess) e = hipMemcpyAsync(P->d_ys, hy.data(), sizeof(double) * D, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(P->d_perm, hp.data(), sizeof(int32_t) * D, hipMemcpyHostToDevice, s);
   if (e == hipSuccess)
-    e = launch_knn(P->d_xs, P->d_ys, D, m, P->d_nbr, P->d_kcnt, P->has_grid ? &P->grid : nullptr, s);
+    e = launch_knn(P->d_xs, P->d_ys, D, m, P->d_nbr, P->d_kcnt, P->has_grid ? &P->grid : nullptr, s, group);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e == hipSuccess) {
     P->kcnt.resize(D);
     e = hipMemcpy(P->kcnt.data(), P->d_kcnt, sizeof(int32_t) * D, hipMemcpyDeviceToHost);
+  }
+  if (e == hipSuccess && group > 1) {
+    std::vector<int32_t> nbr((size_t)D * m);
+    if (m > 0) e = hipMemcpy(nbr.data(), P->d_nbr, sizeof(int32_t) * D * m, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) {
+      set_block_terms(P, group, nbr);
+      e = upload_block_terms(P, s);
+    }
   }
   if (e == hipSuccess && n_obs > 0) {
     std::vector<int32_t> nbr((size_t)D * m);
@@ -328,6 +389,98 @@ vecchia_status vecchia_plan_from_cov(const double* cov_host, int64_t D, const in
   return plan_from_cov_impl(cov_host, D, nbr_host, m, 0, hip_stream, out);
 }
 
+vecchia_status vecchia_plan_block(const double* locs_host, int64_t D, int32_t dim, int32_t ordering,
+                                  const int64_t* perm_in_host, int32_t m, int32_t p, const vecchia_cov* cov,
+                                  void* hip_stream, vecchia_plan_t* out) {
+  vecchia_status st = check_plan_args(dim, m, cov, out);
+  if (st != VECCHIA_OK) return st;
+  if (p < 1 || (int64_t)p * (m + 1) > kMaxVars)
+    return set_error(VECCHIA_E_INVALID, "groups need 1 <= p and p (m + 1) <= 32 variables per term");
+  std::vector<int64_t> perm(D > 0 && D <= 0x7fffffffLL ? D : 0);
+  st = order_impl(locs_host, D, ordering, perm_in_host, perm.data());
+  if (st != VECCHIA_OK) return st;
+  return build_geometry_plan(locs_host, D, std::move(perm), 0, m, cov, hip_stream, out, p);
+}
+
+vecchia_status vecchia_plan_block_terms(vecchia_plan_t plan, int64_t* n_terms, int32_t* var_off_host,
+                                        int32_t* vars_host, int32_t* split_host) {
+  if (!plan || !n_terms) return set_error(VECCHIA_E_INVALID, "null pointer");
+  if (plan->block <= 0) return set_error(VECCHIA_E_INVALID, "not a block plan");
+  *n_terms = plan->n_terms;
+  if (var_off_host) std::memcpy(var_off_host, plan->bvar_off.data(), sizeof(int32_t) * (plan->n_terms + 1));
+  if (vars_host) std::memcpy(vars_host, plan->bvars.data(), sizeof(int32_t) * plan->bvars.size());
+  if (split_host) std::memcpy(split_host, plan->split.data(), sizeof(int32_t) * plan->n_terms);
+  return VECCHIA_OK;
+}
+
+vecchia_status vecchia_plan_from_cov_block(const double* cov_host, int64_t D, const int32_t* var_off_host,
+                                           const int32_t* vars_host, const int32_t* split_host, int64_t n_terms,
+                                           void* hip_stream, vecchia_plan_t* out) {
+  if (!out || !cov_host || !var_off_host || !vars_host || !split_host)
+    return set_error(VECCHIA_E_INVALID, "null pointer");
+  *out = nullptr;
+  if (D < 1 || D > 4096) return set_error(VECCHIA_E_INVALID, "D must be in 1..4096");
+  if (n_terms < 1 || n_terms > 1000000) return set_error(VECCHIA_E_INVALID, "n_terms must be in 1..10^6");
+  for (int64_t a = 0; a < D; ++a)
+    for (int64_t b = 0; b < D; ++b) {
+      const double v = cov_host[a * D + b];
+      if (!std::isfinite(v)) return set_error(VECCHIA_E_INVALID, "non-finite covariance entry");
+      if (v != cov_host[b * D + a]) return set_error(VECCHIA_E_INVALID, "covariance matrix is not symmetric");
+    }
+  if (var_off_host[0] != 0) return set_error(VECCHIA_E_INVALID, "var_off[0] must be 0");
+  int nv_max = 0;
+  for (int64_t g = 0; g < n_terms; ++g) {
+    const int nv = var_off_host[g + 1] - var_off_host[g];
+    if (nv < 1 || nv > kMaxVars) return set_error(VECCHIA_E_INVALID, "every term needs 1..32 variables");
+    if (split_host[g] < 0 || split_host[g] >= nv)
+      return set_error(VECCHIA_E_INVALID, "split must be in 0..(variables - 1)");
+    for (int c = 0; c < nv; ++c) {
+      const int32_t v = vars_host[var_off_host[g] + c];
+      if (v < 0 || v >= D) return set_error(VECCHIA_E_INVALID, "variable index out of range");
+      for (int c2 = 0; c2 < c; ++c2)
+        if (vars_host[var_off_host[g] + c2] == v) return set_error(VECCHIA_E_INVALID, "repeated variable in a term");
+    }
+    nv_max = std::max(nv_max, nv);
+  }
+  auto* P = new (std::nothrow) vecchia_plan_s();
+  if (!P) return set_error(VECCHIA_E_NOMEM, "host allocation");
+  hipGetDevice(&P->device);
+  P->D = D;
+  P->m = 0;
+  P->matrix = true;
+  P->cov = vecchia_cov{VECCHIA_COV_EXPONENTIAL, 0, 0.5, 1.0, 1.0, 0.0};
+  P->perm.resize(D);
+  P->kcnt.assign(D, 0);
+  P->block = 1 << 30;   // explicit terms: no group size
+  P->n_terms = n_terms;
+  P->bvar_off.assign(var_off_host, var_off_host + n_terms + 1);
+  P->bvars.assign(vars_host, vars_host + var_off_host[n_terms]);
+  P->split.assign(split_host, split_host + n_terms);
+  P->sovk.resize(n_terms);
+  for (int64_t g = 0; g < n_terms; ++g) P->sovk[g] = var_off_host[g + 1] - var_off_host[g] - 1;
+  P->block_nv = nv_max;
+  std::vector<int32_t> hp(D);
+  for (int64_t i = 0; i < D; ++i) {
+    P->perm[i] = i;
+    hp[i] = (int32_t)i;
+  }
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  hipError_t e = dev_alloc(&P->d_cov, (size_t)D * D);
+  if (e == hipSuccess) e = dev_alloc(&P->d_perm, D);
+  if (e == hipSuccess) e = dev_alloc(&P->d_kcnt, D);
+  if (e == hipSuccess) e = hipMemcpyAsync(P->d_cov, cov_host, sizeof(double) * D * D, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(P->d_perm, hp.data(), sizeof(int32_t) * D, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(P->d_kcnt, P->kcnt.data(), sizeof(int32_t) * D, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = upload_block_terms(P, s);
+  if (e != hipSuccess) {
+    free_plan_buffers(P);
+    delete P;
+    return hip_error(e, "plan construction");
+  }
+  *out = P;
+  return VECCHIA_OK;
+}
+
 vecchia_status vecchia_plan_from_cov_censored(const double* cov_host, int64_t D, const int32_t* nbr_host,
                                               int32_t m, int64_t n_observed, void* hip_stream,
                                               vecchia_plan_t* out) {
@@ -346,6 +499,7 @@ vecchia_status vecchia_replan(vecchia_plan_t plan, const double* locs_host, int3
   if (plan->matrix) return set_error(VECCHIA_E_INVALID, "a matrix plan has no locations to re-plan");
   if (plan->n_obs > 0)
     return set_error(VECCHIA_E_INVALID, "a censored plan belongs to one replicate; build a new one");
+  if (plan->block > 0) return set_error(VECCHIA_E_INVALID, "a block plan is not re-planned in place; build a new one");
   std::lock_guard<std::mutex> lk(plan->mu);
   if (plan->inflight.load() > 0) return set_error(VECCHIA_E_BUSY, "plan has requests in flight");
   const int64_t D = plan->D;

@@ -87,7 +87,7 @@ __global__ __launch_bounds__(64 * kFinalizeWaves) void term_finalize(
   if (lane == 0) {
     term_res[t] = make_double2(lt, se2);
     if (I.terms_out) {
-      const int64_t u = I.perm[i];
+      const int64_t u = I.bvars ? i : I.perm[i];   // block plans: group order
       I.terms_out[2 * u] = lt;
       I.terms_out[2 * u + 1] = sqrt(se2);
     }
@@ -102,7 +102,7 @@ __global__ __launch_bounds__(kFinalizeThreads) void instance_logsum(const InstDe
   const InstDesc& I = insts[inst_base + (int64_t)blockIdx.x];
   const double2* r = term_res + I.term_base;
   double part_lt = 0.0, part_se = 0.0;
-  for (int64_t i = threadIdx.x; i < I.D; i += kFinalizeThreads) {
+  for (int64_t i = threadIdx.x; i < I.n_terms; i += kFinalizeThreads) {
     const double2 v = r[i];
     part_lt += v.x;
     part_se += v.y;

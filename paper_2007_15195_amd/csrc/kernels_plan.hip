@@ -3,6 +3,9 @@
 // positions j < i with the smallest keys (d^2, j), d^2 = dx*dx + dy*dy in FP64
 // without fused multiply-add, listed in ascending key order.
 //
+// With group = p > 1 (joint block terms, Section 3.2) the candidates of query i
+// are the positions before its group, j < i - i mod p.
+//
 // One wave per query, 8 queries per block. The block stages candidate
 // coordinates through LDS in tiles, in increasing j; lane l of a wave takes the
 // tile's candidates l, l+64, ... (again increasing j) and keeps its own sorted
@@ -23,7 +26,7 @@ __global__ __launch_bounds__(64 * kKnnWaves) void knn_preceding(const double* __
                                                                 const double* __restrict__ ys, int64_t D,
                                                                 int32_t* __restrict__ nbr,
                                                                 int32_t* __restrict__ kcnt, int64_t q_base,
-                                                                int64_t q_end) {
+                                                                int64_t q_end, int group) {
 #pragma clang fp contract(off)
   __shared__ double2 tile[kKnnTile];
   const int lane = threadIdx.x & 63;
@@ -31,6 +34,7 @@ __global__ __launch_bounds__(64 * kKnnWaves) void knn_preceding(const double* __
   const int64_t q0 = q_base + (int64_t)blockIdx.x * kKnnWaves;
   const int64_t i = q0 + wave;
   const bool valid = i < q_end;
+  const int64_t lim_i = group > 1 ? i - i % group : i;   // candidates j < lim_i
   const double qx = valid ? xs[i] : 0.0;
   const double qy = valid ? ys[i] : 0.0;
   double bd[M];
@@ -48,7 +52,7 @@ __global__ __launch_bounds__(64 * kKnnWaves) void knn_preceding(const double* __
       if (j < D) tile[c] = make_double2(xs[j], ys[j]);
     }
     __syncthreads();
-    const int64_t lim = (valid ? i : 0) - t0;
+    const int64_t lim = (valid ? lim_i : 0) - t0;
     const int cmax = (int)(lim < kKnnTile ? (lim > 0 ? lim : 0) : kKnnTile);
     for (int c = lane; c < cmax; c += 64) {
       const double2 p = tile[c];
@@ -72,7 +76,7 @@ __global__ __launch_bounds__(64 * kKnnWaves) void knn_preceding(const double* __
     }
   }
   if (!valid) return;
-  const int k = (int)(i < M ? i : M);
+  const int k = (int)(lim_i < M ? lim_i : M);
   int mine = -1;   // lane s keeps the s-th neighbour
   for (int s = 0; s < k; ++s) {
     double d = bd[0];
@@ -244,7 +248,7 @@ __global__ void fill_i32(int32_t* p, int64_t n, int32_t v) {
 
 template <int M>
 hipError_t knn_dispatch(const double* xs, const double* ys, int64_t D, int32_t* nbr, int32_t* kcnt,
-                        const KnnGrid* grid, hipStream_t s) {
+                        const KnnGrid* grid, int group, hipStream_t s) {
   // queries below q_split scan their i preceding points with a wave each; the
   // rest (large plans only) search the grid, where preceding points are dense
   const int64_t q_split = grid ? (D < kKnnGridMinD ? D : kKnnGridMinD) : D;
@@ -263,7 +267,7 @@ hipError_t knn_dispatch(const double* xs, const double* ys, int64_t D, int32_t* 
     const int64_t n = q_split - b < kPerWave ? q_split - b : kPerWave;
     const unsigned blocks = (unsigned)((n + kKnnWaves - 1) / kKnnWaves);
     hipLaunchKernelGGL(knn_preceding<M>, dim3(blocks), dim3(64 * kKnnWaves), 0, s, xs, ys, D, nbr, kcnt, b,
-                       q_split);
+                       q_split, group);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -272,9 +276,10 @@ hipError_t knn_dispatch(const double* xs, const double* ys, int64_t D, int32_t* 
 
 template <int... Ms>
 hipError_t knn_switch(int m, const double* xs, const double* ys, int64_t D, int32_t* nbr,
-                      int32_t* kcnt, const KnnGrid* grid, hipStream_t s, std::integer_sequence<int, Ms...>) {
+                      int32_t* kcnt, const KnnGrid* grid, int group, hipStream_t s,
+                      std::integer_sequence<int, Ms...>) {
   hipError_t err = hipErrorInvalidValue;
-  ((m == Ms + 1 ? (err = knn_dispatch<Ms + 1>(xs, ys, D, nbr, kcnt, grid, s), 0) : 0), ...);
+  ((m == Ms + 1 ? (err = knn_dispatch<Ms + 1>(xs, ys, D, nbr, kcnt, grid, group, s), 0) : 0), ...);
   return err;
 }
 
@@ -307,8 +312,9 @@ hipError_t launch_fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t s) {
 }
 
 hipError_t launch_knn(const double* xs, const double* ys, int64_t D, int m, int32_t* nbr,
-                      int32_t* kcnt, const KnnGrid* grid, hipStream_t s) {
+                      int32_t* kcnt, const KnnGrid* grid, hipStream_t s, int group) {
   if (D <= 0) return hipSuccess;
+  if (group < 1 || (group > 1 && grid)) return hipErrorInvalidValue;   // the grid search has no group limit
   if (m == 0) {
     hipLaunchKernelGGL(fill_i32, dim3((unsigned)((D + 255) / 256)), dim3(256), 0, s, kcnt, D, 0);
     return hipGetLastError();
@@ -319,7 +325,7 @@ hipError_t launch_knn(const double* xs, const double* ys, int64_t D, int m, int3
     const hipError_t e = build_grid(xs, ys, D, *grid, s);
     if (e != hipSuccess) return e;
   }
-  return knn_switch(m, xs, ys, D, nbr, kcnt, grid, s, std::make_integer_sequence<int, kMaxM>{});
+  return knn_switch(m, xs, ys, D, nbr, kcnt, grid, group, s, std::make_integer_sequence<int, kMaxM>{});
 }
 
 }  // namespace vecchia

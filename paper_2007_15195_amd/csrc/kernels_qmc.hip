@@ -10,7 +10,11 @@
 //     t_a = b'_a - sum_{c<a} L'_ac y_c,   e_a = Phi(t_a)
 //     den = prod_{a<K} e_a,   num = den * e_K
 // (the constant e_0 cancels from the ratio and is left out of the FP32
-// products). The wave writes {sum num, sum den, sum den*(1-e_K)} of its chunk,
+// products). Joint block terms (Section 3.2; the BLOCK variants) keep every
+// factor in the product instead and take the denominator at the term's split s:
+//     den = prod_{a<s} e_a (1 for s = 0),   num = prod_{a<=K} e_a,
+// with 1 - prod_{a>=s} e_a carried as its own recurrence for the FP32 log1p form.
+// The wave writes {sum num, sum den, sum den*(1-e_K)} of its chunk,
 // summed over lanes by a fixed butterfly, so an item's result does not depend on
 // where or with what else it runs.
 //
@@ -88,11 +92,12 @@ __device__ __forceinline__ double* item_out(const InstDesc& I, const Item& it, d
 __device__ __noinline__ double ncdf64(double t) { return normcdf(t); }
 __device__ __noinline__ double ncdfinv64(double u) { return normcdfinv(u); }
 
-template <int K>
+template <int K, bool BLOCK>
 __device__ __forceinline__ void item_f64(const Item& it, const Aux64* __restrict__ aux64,
                                          const uint64_t* __restrict__ Zg, double* __restrict__ sums) {
   const InstDesc& I = *it.I;
   const int lane = threadIdx.x & 63;
+  const int sp = BLOCK ? uniform(I.split[it.i]) : K;   // denominator: the first sp factors
   const double* __restrict__ prep = reinterpret_cast<const double*>(I.prep) + it.i * I.prep_stride;
   const double e0 = aux64[it.t].e0;
   const int p_begin = 1 + it.c * I.chunk_points;
@@ -112,9 +117,11 @@ __device__ __forceinline__ void item_f64(const Item& it, const Aux64* __restrict
     const bool live = p0 + lane <= p_last;
     double y[K];
     double e = e0, prod = e0;
+    double head = 1.0;   // BLOCK: prod_{a<sp} e_a
     bool alive = e0 > 0.0;
 #pragma unroll
     for (int a = 1; a <= K; ++a) {
+      if (BLOCK && a == sp) head = prod;
       const double w = lattice_coord_f64(U[a - 1]);
       U[a - 1] += Zg[a - 1] << 6;
       const double u = fmax(w * e, 2.2250738585072014e-308);
@@ -125,11 +132,16 @@ __device__ __forceinline__ void item_f64(const Item& it, const Aux64* __restrict
       for (int c = 0; c < a; ++c) acc -= row[c] * y[c];
       e = alive ? ncdf64(acc) : 0.0;
       alive = alive && e > 0.0;
-      if (a < K) prod *= e;
+      if (BLOCK || a < K) prod *= e;
     }
     if (live) {
-      acc_den += prod;
-      acc_num += prod * e;
+      if (BLOCK) {
+        acc_den += head;
+        acc_num += prod;
+      } else {
+        acc_den += prod;
+        acc_num += prod * e;
+      }
     }
   }
   acc_num = wave_sum(acc_num);
@@ -153,11 +165,12 @@ constexpr float kDeepV = 7.74596669f;   // sqrt(60)
 // steps that need them. The product of e_1..e_{K-1} is qm * 2^qe (qe an
 // integer), renormalised when some lane's qm falls below 2^-50; every factor
 // is >= 2^-65, so qm never leaves the normal range.
-template <int K>
+template <int K, bool BLOCK>
 __device__ __forceinline__ void item_f32(const Item& it, const Aux32* __restrict__ aux32,
                                          const uint64_t* __restrict__ Zg, double* __restrict__ sums) {
   const InstDesc& I = *it.I;
   const int lane = threadIdx.x & 63;
+  const int sp = BLOCK ? uniform(I.split[it.i]) : K;   // denominator: the first sp factors
   const float* __restrict__ prep = reinterpret_cast<const float*>(I.prep) + it.i * I.prep_stride;
   const Aux32 ax = aux32[it.t];
   const bool split0 = uniform(ax.en0 != 0.0f) != 0;
@@ -187,8 +200,21 @@ __device__ __forceinline__ void item_f32(const Item& it, const Aux32* __restrict
     bool split = split0;
     float qm = 1.0f;
     int qe = 0;
+    float dm = 1.0f;   // BLOCK: prod_{a<sp} e_a = dm 2^de
+    int de = 0;
+    float cc = 0.0f;   // BLOCK: 1 - prod_{sp<=a} e_a so far
+    if (BLOCK) {
+      // every factor is in the products, e_0 included
+      qe = (int)ax.en0 + __builtin_amdgcn_frexp_expf(ax.em0);
+      qm = __builtin_amdgcn_frexp_mantf(ax.em0);
+      if (sp == 0) cc = ax.ec0;
+    }
 #pragma unroll
     for (int a = 1; a <= K; ++a) {
+      if (BLOCK && a == sp) {
+        dm = qm;
+        de = qe;
+      }
       const int ro = a * (a + 1) / 2;
       const CoordF32 wp = lattice_coord_f32((uint32_t)(U[a - 1] >> 32));
       U[a - 1] += Zg[a - 1] << 6;
@@ -220,11 +246,15 @@ __device__ __forceinline__ void item_f32(const Item& it, const Aux32* __restrict
           const float fl = floorf(fmaxf(ph.f, -1048576.0f));
           em = fast_exp2(fmaxf(ph.f, -1048576.0f) - fl) * ph.R;
           en = fl;
-          if (a < K) qe += (int)fl;
+          if (BLOCK || a < K) qe += (int)fl;
         }
         split = true;
       }
-      if (a < K) {
+      if (BLOCK && a >= sp) {
+        const float eca = neg ? 1.0f - ldexpf(em, (int)en) : m;
+        cc = fmaf(eca, 1.0f - cc, cc);
+      }
+      if (BLOCK || a < K) {
         qm *= em;
         const bool low = qm < 0x1p-50f;
         if (__builtin_expect(any_lane(low), 0)) {
@@ -237,14 +267,22 @@ __device__ __forceinline__ void item_f32(const Item& it, const Aux32* __restrict
     }
     // den = prod_{a<K} e_a, num = den e_K, cnum = den (1 - e_K); lanes past the
     // chunk's last point contribute zero
-    const float qml = p0 + lane <= p_last ? qm : 0.0f;
-    const int enk = (int)en;
-    const double den = ldexp((double)qml, qe);
-    const double num = ldexp(den * (double)em, enk);
-    const float ec = neg ? 1.0f - ldexpf(em, enk) : m;
-    acc_den += den;
-    acc_num += num;
-    acc_cnum = fma(den, (double)ec, acc_cnum);
+    const bool in_chunk = p0 + lane <= p_last;
+    if (BLOCK) {
+      const double den = ldexp((double)(in_chunk ? dm : 0.0f), de);
+      acc_den += den;
+      acc_num += ldexp((double)(in_chunk ? qm : 0.0f), qe);
+      acc_cnum = fma(den, (double)cc, acc_cnum);
+    } else {
+      const float qml = in_chunk ? qm : 0.0f;
+      const int enk = (int)en;
+      const double den = ldexp((double)qml, qe);
+      const double num = ldexp(den * (double)em, enk);
+      const float ec = neg ? 1.0f - ldexpf(em, enk) : m;
+      acc_den += den;
+      acc_num += num;
+      acc_cnum = fma(den, (double)ec, acc_cnum);
+    }
   }
   acc_num = wave_sum(acc_num);
   acc_den = wave_sum(acc_den);
@@ -263,17 +301,17 @@ __device__ __forceinline__ void item_f32(const Item& it, const Aux32* __restrict
 constexpr int f32_min_waves(int K) { return K <= 30 ? 4 : 3; }
 constexpr int f64_min_waves(int K) { return K <= 11 ? 4 : K <= 18 ? 3 : 2; }
 
-template <int K>
+template <int K, bool BLOCK>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(f64_min_waves(K)))) void qmc_f64(
     const InstDesc* __restrict__ insts, const RangeDesc* __restrict__ ranges, int n_ranges,
     const Aux64* __restrict__ aux64, const uint64_t* __restrict__ Zg, double* __restrict__ sums,
     int64_t item_base) {
   const Item it = decode_item(insts, ranges, n_ranges, item_base + (int64_t)blockIdx.x);
-  item_f64<K>(it, aux64, Zg, sums);
+  item_f64<K, BLOCK>(it, aux64, Zg, sums);
 }
 
 
-template <int K>
+template <int K, bool BLOCK>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(f32_min_waves(K)))) void qmc_f32(
     const InstDesc* __restrict__ insts,
                                               const RangeDesc* __restrict__ ranges, int n_ranges,
@@ -281,10 +319,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(f32_min_wave
                                               const uint64_t* __restrict__ Zg, double* __restrict__ sums,
                                               int64_t item_base) {
   const Item it = decode_item(insts, ranges, n_ranges, item_base + (int64_t)blockIdx.x);
-  item_f32<K>(it, aux32, Zg, sums);
+  item_f32<K, BLOCK>(it, aux32, Zg, sums);
 }
 
-template <int K>
+template <int K, bool BLOCK>
 hipError_t qmc_dispatch(int precision, const InstDesc* insts, const RangeDesc* ranges, int n_ranges,
                         int64_t n_items, const Aux64* aux64, const Aux32* aux32, const uint64_t* Z,
                         double* sums, hipStream_t s) {
@@ -293,34 +331,37 @@ hipError_t qmc_dispatch(int precision, const InstDesc* insts, const RangeDesc* r
   for (int64_t b = 0; b < n_items; b += kPer) {
     const unsigned n = (unsigned)(n_items - b < kPer ? n_items - b : kPer);
     if (precision == VECCHIA_FP32_LOOP)
-      hipLaunchKernelGGL(qmc_f32<K>, dim3(n), dim3(64), 0, s, insts, ranges, n_ranges, aux32, Z, sums, b);
+      hipLaunchKernelGGL((qmc_f32<K, BLOCK>), dim3(n), dim3(64), 0, s, insts, ranges, n_ranges, aux32, Z, sums, b);
     else
-      hipLaunchKernelGGL(qmc_f64<K>, dim3(n), dim3(64), 0, s, insts, ranges, n_ranges, aux64, Z, sums, b);
+      hipLaunchKernelGGL((qmc_f64<K, BLOCK>), dim3(n), dim3(64), 0, s, insts, ranges, n_ranges, aux64, Z, sums, b);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
 }
 
-template <int... Ks>
+template <bool BLOCK, int... Ks>
 hipError_t qmc_switch(int K, int precision, const InstDesc* insts, const RangeDesc* ranges,
                       int n_ranges, int64_t n_items, const Aux64* aux64, const Aux32* aux32,
                       const uint64_t* Z, double* sums, hipStream_t s, std::integer_sequence<int, Ks...>) {
   hipError_t err = hipErrorInvalidValue;
-  ((K == Ks + 1 ? (err = qmc_dispatch<Ks + 1>(precision, insts, ranges, n_ranges, n_items, aux64,
-                                              aux32, Z, sums, s), 0) : 0), ...);
+  ((K == Ks + 1 ? (err = qmc_dispatch<Ks + 1, BLOCK>(precision, insts, ranges, n_ranges, n_items, aux64,
+                                                     aux32, Z, sums, s), 0) : 0), ...);
   return err;
 }
 
 }  // namespace
 
-hipError_t launch_qmc(int K, int precision, const InstDesc* d_insts, const RangeDesc* d_ranges,
+hipError_t launch_qmc(int K, int precision, bool block, const InstDesc* d_insts, const RangeDesc* d_ranges,
                       int n_ranges, int64_t n_items, const Aux64* aux64, const Aux32* aux32,
                       const uint64_t* d_Z, double* sums, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
   if (K < 1 || K > kMaxM) return hipErrorInvalidValue;
-  return qmc_switch(K, precision, d_insts, d_ranges, n_ranges, n_items, aux64, aux32, d_Z, sums, s,
-                    std::make_integer_sequence<int, kMaxM>{});
+  if (block)
+    return qmc_switch<true>(K, precision, d_insts, d_ranges, n_ranges, n_items, aux64, aux32, d_Z, sums, s,
+                            std::make_integer_sequence<int, kMaxM>{});
+  return qmc_switch<false>(K, precision, d_insts, d_ranges, n_ranges, n_items, aux64, aux32, d_Z, sums, s,
+                           std::make_integer_sequence<int, kMaxM>{});
 }
 
 }  // namespace vecchia

@@ -20,6 +20,10 @@
 // Gaussian conditional density of eq. (4) at scale r, times the Jacobian 1 / r:
 //     log f = -log(2 pi)/2 - log L_kk - z^2/2 + log(1/r),  z = (b_k - sum_{c<k} L_kc w_c) / L_kk.
 //
+// Block plans (joint terms, Section 3.2): term i's variables are listed
+// explicitly (conditioning set first, then the group) and the rows of all of
+// them are written; the QMC kernel takes the denominator at the term's split.
+//
 // A pivot <= 0 (or NaN) marks the term NOT_PD: its outputs become NaN and the
 // instance's bad_term is lowered to i.
 #include "fp32_math_coeffs.h"
@@ -61,11 +65,14 @@ __global__ __launch_bounds__(64) void term_setup(const InstDesc* __restrict__ in
   const int ii = find_inst(term_bases, n_inst, t);
   const InstDesc& I = insts[ii];
   const int64_t i = t - term_bases[ii];
-  const int k = I.kcnt[i];
+  const bool blk = I.bvars != nullptr;
+  const int boff = blk ? I.bvar_off[i] : 0;
+  const int k = blk ? I.bvar_off[i + 1] - boff - 1 : I.kcnt[i];
   const int n = k + 1;
   // variable slot of each lane's neighbour: observed neighbours first (censored
   // plans only), each group in the stored order, i last
-  const int64_t v = lane < k ? (int64_t)I.nbr[i * I.m + lane] : i;
+  const int64_t v = blk ? (lane < n ? (int64_t)I.bvars[boff + lane] : 0)
+                        : (lane < k ? (int64_t)I.nbr[i * I.m + lane] : i);
   const bool eq = lane < k && v < I.n_obs;
   const uint64_t eq_mask = __ballot(eq);
   const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));

@@ -8,6 +8,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <tuple>
 
 namespace vecchia {
 
@@ -206,7 +207,7 @@ vecchia_status Batch::create(const std::vector<vecchia_plan_s*>& plans,
   b->prep_off_.resize(n);
   int64_t tb = 0, sb = 0;
   size_t prep = 0;
-  std::map<std::pair<int, int>, std::vector<RangeDesc>> by_k;   // (K, precision) -> ranges
+  std::map<std::tuple<int, int, bool>, std::vector<RangeDesc>> by_k;   // (K, precision, block) -> ranges
   for (int j = 0; j < n; ++j) {
     vecchia_plan_s* P = plans[j];
     std::string why;
@@ -215,7 +216,7 @@ vecchia_status Batch::create(const std::vector<vecchia_plan_s*>& plans,
     if (!valid_qmc(qmcs[j], &why)) return set_error(VECCHIA_E_INVALID, "instance " + std::to_string(j) + ": " + why);
     const int R = qmcs[j].n_shifts;
     const int prec = qmcs[j].precision;
-    const int nv = P->m + 1;
+    const int nv = P->block > 0 ? P->block_nv : P->m + 1;   // variables per term, at most
     const int stride = (int)align_up((size_t)nv * (nv + 1) / 2, prec == VECCHIA_FP32_LOOP ? 4 : 2);
     InstDesc& d = b->desc_[j];
     std::memset(&d, 0, sizeof(d));
@@ -225,9 +226,13 @@ vecchia_status Batch::create(const std::vector<vecchia_plan_s*>& plans,
     d.perm = P->d_perm;
     d.nbr = P->d_nbr;
     d.kcnt = P->d_kcnt;
-    d.sovk = P->n_obs > 0 ? P->d_sovk : P->d_kcnt;
+    d.sovk = (P->n_obs > 0 || P->block > 0) ? P->d_sovk : P->d_kcnt;   // as sov_dims()
     d.n_obs = P->n_obs;
     d.D = P->D;
+    d.n_terms = P->terms();
+    d.bvar_off = P->block > 0 ? P->d_bvar_off : nullptr;
+    d.bvars = P->block > 0 ? P->d_bvars : nullptr;
+    d.split = P->block > 0 ? P->d_split : nullptr;
     d.term_base = tb;
     d.sums_base = sb;
     d.m = P->m;
@@ -241,15 +246,16 @@ vecchia_status Batch::create(const std::vector<vecchia_plan_s*>& plans,
     const int C = d.n_chunks;
     b->term_bases_[j] = tb;
     b->prep_off_[j] = prep;
-    prep += align_up((size_t)P->D * stride * (prec == VECCHIA_FP32_LOOP ? 4 : 8), 256);
+    const int64_t NT = P->terms();
+    prep += align_up((size_t)NT * stride * (prec == VECCHIA_FP32_LOOP ? 4 : 8), 256);
     if (prec == VECCHIA_FP32_LOOP) b->any_f32_ = true;
     // runs of equal k >= 1 become ranges of the launch for that k
     const std::vector<int32_t>& sk = P->sov_dims();
     int64_t i = 0;
-    while (i < P->D) {
+    while (i < NT) {
       const int k = sk[i];
       int64_t e = i + 1;
-      while (e < P->D && sk[e] == k) ++e;
+      while (e < NT && sk[e] == k) ++e;
       if (k >= 1) {
         RangeDesc r;
         r.item_begin = e - i;   // term count; turned into the item prefix below
@@ -258,14 +264,14 @@ vecchia_status Batch::create(const std::vector<vecchia_plan_s*>& plans,
         r.K = k;
         r.items_per_term = R * C;
         r.n_chunks = C;
-        by_k[{k, prec}].push_back(r);
+        by_k[{k, prec, P->block > 0}].push_back(r);
       }
       i = e;
     }
-    if ((int64_t)R * C > 0x7fffffffLL / std::max<int64_t>(1, P->D))
+    if ((int64_t)R * C > 0x7fffffffLL / std::max<int64_t>(1, NT))
       return set_error(VECCHIA_E_INVALID, "instance " + std::to_string(j) + " has more than 2^31 work items");
-    tb += P->D;
-    sb += P->D * (int64_t)R * C;
+    tb += NT;
+    sb += NT * (int64_t)R * C;
   }
   b->term_bases_[n] = tb;
   b->total_terms_ = tb;
@@ -276,8 +282,9 @@ vecchia_status Batch::create(const std::vector<vecchia_plan_s*>& plans,
   // caller's stream, the others (mostly the few terms with k < m) run beside it
   for (auto it = by_k.begin(); it != by_k.end(); ++it) {
     Launch L;
-    L.K = it->first.first;
-    L.precision = it->first.second;
+    L.K = std::get<0>(it->first);
+    L.precision = std::get<1>(it->first);
+    L.block = std::get<2>(it->first);
     L.range_off = (int)b->ranges_.size();
     L.n_ranges = (int)it->second.size();
     int64_t items = 0;
@@ -395,7 +402,7 @@ vecchia_status Batch::enqueue(hipStream_t s) {
       if (e == hipSuccess) e = hipEventRecord(a, ls);
       if (e != hipSuccess) break;
     }
-    e = launch_qmc(L.K, L.precision, d_desc_, d_ranges_ + L.range_off, L.n_ranges, L.n_items,
+    e = launch_qmc(L.K, L.precision, L.block, d_desc_, d_ranges_ + L.range_off, L.n_ranges, L.n_items,
                    d_aux64_, d_aux32_, d_Z_, d_sums_, ls);
     if (prof && e == hipSuccess) {
       e = hipEventRecord(b, ls);
@@ -559,7 +566,7 @@ vecchia_status Batch::time_main_launch(hipStream_t s, int reps, float* median_ms
   for (int r = 0; r < reps && e == hipSuccess; ++r) {
     e = hipEventRecord(ev[2 * r], s);
     if (e == hipSuccess)
-      e = launch_qmc(L.K, L.precision, d_desc_, d_ranges_ + L.range_off, L.n_ranges, L.n_items, d_aux64_,
+      e = launch_qmc(L.K, L.precision, L.block, d_desc_, d_ranges_ + L.range_off, L.n_ranges, L.n_items, d_aux64_,
                      d_aux32_, d_Z_, d_sums_, s);
     if (e == hipSuccess) e = hipEventRecord(ev[2 * r + 1], s);
   }

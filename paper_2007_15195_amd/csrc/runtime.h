@@ -70,6 +70,7 @@ class Batch {
   struct Launch {
     int K;
     int precision;
+    bool block;
     int range_off;
     int n_ranges;
     int64_t n_items;
@@ -148,7 +149,18 @@ struct vecchia_plan_s {
   int64_t n_obs = 0;
   std::vector<int32_t> sovk;
   int32_t* d_sovk = nullptr;
-  const std::vector<int32_t>& sov_dims() const { return n_obs > 0 ? sovk : kcnt; }
+  // block plans (joint terms of p sites, Section 3.2): n_terms groups, each with
+  // its variable list (CSR, conditioning set first) and denominator split;
+  // sovk holds each term's SOV dimension (variables - 1)
+  int32_t block = 0;
+  int32_t block_nv = 0;            // most variables of any term
+  int64_t n_terms = 0;
+  std::vector<int32_t> bvar_off, bvars, split;
+  int32_t* d_bvar_off = nullptr;
+  int32_t* d_bvars = nullptr;
+  int32_t* d_split = nullptr;
+  const std::vector<int32_t>& sov_dims() const { return (n_obs > 0 || block > 0) ? sovk : kcnt; }
+  int64_t terms() const { return block > 0 ? n_terms : D; }
   double* d_xs = nullptr;
   double* d_ys = nullptr;
   double* d_cov = nullptr;

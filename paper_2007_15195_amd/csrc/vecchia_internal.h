@@ -29,6 +29,13 @@ struct InstDesc {
   double* terms_out;       // D x 2 user order, or null
   void* prep;              // per-term scaled Cholesky rows (double or float), term 0
   int64_t D;
+  int64_t n_terms;         // terms: D, or the number of groups of a block plan
+  // block plans (joint terms, Section 3.2): term i's variables are
+  // bvars[bvar_off[i] .. bvar_off[i+1]) (plan indices, conditioning set first);
+  // its denominator is the CDF of the first split[i] of them. Null otherwise.
+  const int32_t* bvar_off;
+  const int32_t* bvars;
+  const int32_t* split;
   int64_t n_obs;           // plan positions < n_obs are uncensored sites (eq. (11)); 0 = plain
   int64_t term_base;       // global index of plan term 0 (aux arrays)
   int64_t sums_base;       // index of (term 0, shift 0, chunk 0) in the sums triples
@@ -79,12 +86,14 @@ struct KnnGrid {
 constexpr int64_t kKnnGridMinD = 16384;
 
 // Launchers (kernels_*.hip).
+// group > 1: query i's candidates are j < i - i mod group (no grid then).
 hipError_t launch_knn(const double* xs, const double* ys, int64_t D, int m, int32_t* nbr,
-                      int32_t* kcnt, const KnnGrid* grid, hipStream_t s);
+                      int32_t* kcnt, const KnnGrid* grid, hipStream_t s, int group = 1);
 hipError_t launch_fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t s);
 hipError_t launch_setup(const InstDesc* d_insts, int n_inst, const int64_t* d_term_bases,
                         int64_t total_terms, Aux64* aux64, Aux32* aux32, hipStream_t s);
-hipError_t launch_qmc(int K, int precision, const InstDesc* d_insts, const RangeDesc* d_ranges,
+// block: the launch's instances are block plans (denominator split per term).
+hipError_t launch_qmc(int K, int precision, bool block, const InstDesc* d_insts, const RangeDesc* d_ranges,
                       int n_ranges, int64_t n_items, const Aux64* aux64, const Aux32* aux32,
                       const uint64_t* d_Z, double* sums, hipStream_t s);
 // Scale-mixture quadrature weights (log), passed by value to the combine kernel.

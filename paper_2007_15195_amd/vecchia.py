@@ -35,7 +35,7 @@ EXPORTED = [
     "vecchia_mixture_logcdf", "vecchia_mixture_rule", "vecchia_mixture_search",
     "vecchia_plan_censored", "vecchia_plan_from_cov_censored", "vecchia_plan_censoring",
     "vecchia_mixbatch_create", "vecchia_mixbatch_logcdf", "vecchia_mixbatch_status", "vecchia_mixbatch_destroy",
-    "vecchia_map_anisotropic",
+    "vecchia_map_anisotropic", "vecchia_plan_block", "vecchia_plan_block_terms", "vecchia_plan_from_cov_block",
 ]
 
 
@@ -87,6 +87,11 @@ def lib():
         "vecchia_mixbatch_status": [c_void_p, c_void_p],
         "vecchia_mixbatch_destroy": [c_void_p],
         "vecchia_map_anisotropic": [c_void_p, c_int64, c_double, c_double, c_void_p],
+        "vecchia_plan_block": [c_void_p, c_int64, c_int32, c_int32, c_void_p, c_int32, c_int32, POINTER(vecchia_cov),
+                               c_void_p, POINTER(c_void_p)],
+        "vecchia_plan_block_terms": [c_void_p, POINTER(c_int64), c_void_p, c_void_p, c_void_p],
+        "vecchia_plan_from_cov_block": [c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_int64, c_void_p,
+                                        POINTER(c_void_p)],
         "vecchia_replan": [c_void_p, c_void_p, c_int32, c_void_p, c_void_p],
         "vecchia_plan_info": [c_void_p, POINTER(c_int64), POINTER(c_int32)],
         "vecchia_plan_neighbours": [c_void_p, c_void_p, c_void_p],
@@ -273,6 +278,15 @@ def vecchia_plan_neighbours(plan: int):
     return perm, nbr[:, :m]
 
 
+def plan_n_terms(plan: int) -> int:
+    """Terms of a plan: D, or the number of joint terms of a block plan."""
+    D, _ = vecchia_plan_info(plan)
+    n = c_int64()
+    if lib().vecchia_plan_block_terms(plan, byref(n), None, None, None) == VECCHIA_OK:
+        return n.value
+    return D
+
+
 def vecchia_logcdf(plan: int, x, qmc, out, scale: float = 1.0, cov_override=None, terms=None,
                    stream=None) -> None:
     D, _ = vecchia_plan_info(plan)
@@ -281,7 +295,7 @@ def vecchia_logcdf(plan: int, x, qmc, out, scale: float = 1.0, cov_override=None
     _check(lib().vecchia_logcdf(plan, _dev_ptr(x, D, "x"), float(scale),
                                 None if c is None else ctypes.addressof(c), byref(q),
                                 _dev_ptr(out, 2, "out"),
-                                None if terms is None else _dev_ptr(terms, 2 * D, "terms"),
+                                None if terms is None else _dev_ptr(terms, 2 * plan_n_terms(plan), "terms"),
                                 _stream_ptr(stream)))
 
 
@@ -478,4 +492,44 @@ def vecchia_map_anisotropic(locs: np.ndarray, phi: float, A: float) -> np.ndarra
     out = np.empty_like(locs)
     _check(lib().vecchia_map_anisotropic(locs.ctypes.data, locs.shape[0], float(phi), float(A), out.ctypes.data))
     return out
+
+
+def vecchia_plan_block(locs: np.ndarray, ordering: int, m: int, p: int, cov, perm=None, stream=None) -> int:
+    """Joint block plan: groups of p consecutive plan positions (Section 3.2)."""
+    locs = np.ascontiguousarray(locs, dtype=np.float64)
+    if locs.ndim != 2:
+        raise ValueError("locs must be D x dim")
+    pin = None if perm is None else np.ascontiguousarray(perm, dtype=np.int64)
+    h = c_void_p()
+    c = as_cov(cov)
+    _check(lib().vecchia_plan_block(locs.ctypes.data, locs.shape[0], locs.shape[1], int(ordering),
+                                    None if pin is None else pin.ctypes.data, int(m), int(p), byref(c),
+                                    _stream_ptr(stream), byref(h)))
+    return h.value
+
+
+def vecchia_plan_block_terms(plan: int):
+    """(var_off, vars, split) of a block plan."""
+    n = c_int64()
+    _check(lib().vecchia_plan_block_terms(plan, byref(n), None, None, None))
+    off = np.empty(n.value + 1, dtype=np.int32)
+    split = np.empty(n.value, dtype=np.int32)
+    _check(lib().vecchia_plan_block_terms(plan, byref(n), off.ctypes.data, None, split.ctypes.data))
+    var = np.empty(max(1, int(off[-1])), dtype=np.int32)
+    _check(lib().vecchia_plan_block_terms(plan, byref(n), None, var.ctypes.data, None))
+    return off, var[:int(off[-1])], split
+
+
+def vecchia_plan_from_cov_block(Sigma: np.ndarray, terms, stream=None) -> int:
+    """terms: list of (variables, split) pairs over an explicit covariance."""
+    Sigma = np.ascontiguousarray(Sigma, dtype=np.float64)
+    off = np.zeros(len(terms) + 1, dtype=np.int32)
+    for g, (v, _) in enumerate(terms):
+        off[g + 1] = off[g] + len(v)
+    var = np.ascontiguousarray(np.concatenate([np.asarray(v, dtype=np.int32) for v, _ in terms]), dtype=np.int32)
+    split = np.array([sp for _, sp in terms], dtype=np.int32)
+    h = c_void_p()
+    _check(lib().vecchia_plan_from_cov_block(Sigma.ctypes.data, Sigma.shape[0], off.ctypes.data, var.ctypes.data,
+                                             split.ctypes.data, len(terms), _stream_ptr(stream), byref(h)))
+    return h.value
 

@@ -244,3 +244,16 @@ def test_mahalanobis_special_cases():
     assert abs(C.mahalanobis_distance([1.0, 2.0], [0.0, 0.0], 0.0, 3.0) - math.hypot(1.0, 6.0)) < 1e-14
     assert abs(C.mahalanobis_distance([1.0, 2.0], [0.0, 0.0], math.pi / 2, 3.0) - math.hypot(2.0, 3.0)) < 1e-14
     assert abs(C.mahalanobis_distance([0.3, -0.4], [0.0, 0.0], 0.7, 1.0) - 0.5) < 1e-15
+
+
+def test_block_plan_arguments_rejected_on_the_host():
+    locs = np.random.default_rng(1).random((20, 2))
+    cov = V.make_cov(V.VECCHIA_COV_MATERN, 1.5, 1.0, 0.1, 0.0)
+    for m, p in ((10, 3), (4, 7), (1, 0), (0, 33)):
+        with pytest.raises(V.VecchiaError) as e:
+            V.vecchia_plan_block(locs, W.ORDER_COORD, m, p, cov, stream=0)
+        assert e.value.status == 1
+    S = np.eye(4)
+    for terms in ([([0, 1], 2)], [([0, 0], 1)], [([0, 5], 1)], [([], 0)], [(list(range(4)), -1)]):
+        with pytest.raises(V.VecchiaError):
+            V.vecchia_plan_from_cov_block(S, terms, stream=0)
