@@ -23,6 +23,10 @@ Modules:
   covariance  exponential / Matern covariance with a nugget.
   sov         one Vecchia term: Cholesky + SOV chain + QMC mean and SE.
   vecchia     the whole log-CDF: order, neighbours, terms, log-space sum.
+  mixture     the scale-mixture outer integral over R (eqs. (8)-(9), (11)).
+  censored    the censored likelihood of one replicate in Vecchia form (eq. (11)).
+  block       joint (block) conditional terms (Section 3.2).
+  fullsov     the full-dimension SOV estimate, the paper's comparator (Section 3.1).
 
 Where the paper leaves a point open (orderings, ties, lattice, shifts, SE,
 shared numerator/denominator points), the module that takes the reading says
@@ -30,5 +34,5 @@ which one it takes in its own header. Parity of the Vecchia approximation itself
 m < D-1 and a general covariance is unpinned (no closed form exists); the tests
 pin every component and the exact special cases instead.
 """
-from . import lattice, ordering, neighbours, covariance, sov, vecchia, mixture, censored, block  # noqa: F401
+from . import lattice, ordering, neighbours, covariance, sov, vecchia, mixture, censored, block, fullsov  # noqa: F401
 from .vecchia import logcdf, logcdf_from_cov, plan  # noqa: F401

@@ -66,6 +66,14 @@ def shift(seed: int, term: int, r: int, dim: int) -> int:
     return splitmix64_output(seed, (term << 21) | (r << 5) | dim)
 
 
+def full_shift(seed: int, r: int, dim: int) -> int:
+    """Random shift of dimension `dim` in replicate `r` of the full-dimension
+    estimator (oracle.fullsov): SplitMix64 output n = 2^63 + r 2^32 + dim, a
+    range no Vecchia term's key reaches."""
+    assert 0 <= r < MAX_SHIFTS and 0 <= dim < (1 << 32)
+    return splitmix64_output(seed, (1 << 63) | (r << 32) | dim)
+
+
 def lattice_u(p: np.ndarray, Z: int, S: int) -> np.ndarray:
     """U = (p * Z + S) mod 2^64 for an array of point indices p (uint64)."""
     p = np.asarray(p, dtype=np.uint64)
