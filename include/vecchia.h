@@ -346,6 +346,23 @@ vecchia_status vecchia_mixbatch_status(vecchia_mixbatch_t mb, int64_t* bad_terms
 /* Wait for outstanding work and free the batch. */
 vecchia_status vecchia_mixbatch_destroy(vecchia_mixbatch_t mb);
 
+/* Full-dimension SOV estimate of log Phi_D(x / scale) on the plan's ordering
+ * and covariance: Genz's separation of variables over all D variables with a
+ * (D-1)-dimensional randomized lattice (the comparator the paper checks the
+ * Vecchia approximation against, Section 3.1, Figures 1-4). Builds the dense
+ * covariance and its Cholesky factor on the device (blocked, FP64), then
+ * evaluates every lattice point's chain with its product kept as a sum of
+ * log Phi. Lattice: Z_j from the first D-1 primes; the shift of dimension j in
+ * replicate r is SplitMix64 output 2^63 + r 2^32 + j of q->seed.
+ * out_dev = {log F, delta-method SE over the shifts} (device); NaN when the
+ * covariance is not positive definite. q->precision must be VECCHIA_FP64 and
+ * q->n_shifts at most 1024. Workspace D^2 + (D-1) N R doubles, kept in the
+ * plan and grown on demand (at most 64 GB; D <= 40000). Asynchronous on
+ * hip_stream. Errors: INVALID (censored plan, FP32, sizes), NOMEM, HIP. */
+vecchia_status vecchia_full_logcdf(vecchia_plan_t plan, const double* x_dev, double scale,
+                                   const vecchia_cov* cov_override, const vecchia_qmc* q, double* out_dev,
+                                   void* hip_stream);
+
 /* Launch-shape autotuner (the batched launch of Section 2.2, eq. (6): terms of
  * all instances that share K run in one launch, one wave per work item of
  * chunk_points lattice points of one shift of one term). For each K = ms[k]

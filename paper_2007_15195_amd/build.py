@@ -33,6 +33,7 @@ SOURCES = [
     "autotune.cpp",
     "calibrate.hip",
     "mixture.cpp",
+    "fullsov.hip",
 ]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-function",

@@ -42,6 +42,7 @@ void free_plan_buffers(vecchia_plan_s* P) {
   hipFree(P->d_bvars);
   hipFree(P->d_split);
   hipFree(P->d_mix);
+  hipFree(P->d_full);
   if (P->has_grid) {
     hipFree(P->grid.cell);
     hipFree(P->grid.start);

@@ -21,7 +21,8 @@ std::map<int, uint64_t*> g_Z;
 // exact condition (f 2^64 + Z)^2 <= p 2^128 with f = floor(sqrt(p)), i.e.
 // Z^2 + 2 f Z 2^64 <= (p - f^2) 2^128, evaluated in three 64-bit limbs.
 uint64_t frac_sqrt_fixed(uint64_t p) {
-  uint64_t f = 0;
+  uint64_t f = (uint64_t)std::sqrt((double)p);
+  while (f * f > p) --f;
   while ((f + 1) * (f + 1) <= p) ++f;
   const uint64_t c = p - f * f;
   auto fits = [&](uint64_t Z) {
@@ -43,6 +44,46 @@ uint64_t frac_sqrt_fixed(uint64_t p) {
   return Z;
 }
 }  // namespace
+
+namespace {
+std::map<int, std::pair<uint64_t*, int>> g_Zn;   // device -> (table, length)
+}  // namespace
+
+const uint64_t* device_lattice_table_n(int device, int n, hipError_t* err) {
+  std::lock_guard<std::mutex> lk(g_dev_mu);
+  auto it = g_Zn.find(device);
+  if (it != g_Zn.end() && it->second.second >= n) {
+    *err = hipSuccess;
+    return it->second.first;
+  }
+  const int len = std::max(n, it != g_Zn.end() ? 2 * it->second.second : 64);
+  std::vector<uint64_t> primes;
+  primes.reserve(len);
+  for (uint64_t c = 2; (int)primes.size() < len; ++c) {
+    bool prime = true;
+    for (uint64_t q : primes) {
+      if (q * q > c) break;
+      if (c % q == 0) {
+        prime = false;
+        break;
+      }
+    }
+    if (prime) primes.push_back(c);
+  }
+  std::vector<uint64_t> Z(len);
+  for (int j = 0; j < len; ++j) Z[j] = frac_sqrt_fixed(primes[j]);
+  uint64_t* d = nullptr;
+  *err = hipMalloc(&d, sizeof(uint64_t) * len);
+  if (*err != hipSuccess) return nullptr;
+  *err = hipMemcpy(d, Z.data(), sizeof(uint64_t) * len, hipMemcpyHostToDevice);
+  if (*err != hipSuccess) {
+    hipFree(d);
+    return nullptr;
+  }
+  // an older, shorter table is kept (a call in flight may still read it)
+  g_Zn[device] = {d, len};
+  return d;
+}
 
 namespace {
 struct ProfRec {

@@ -22,6 +22,9 @@ hipError_t profile_events(hipEvent_t* a, hipEvent_t* b);
 void profile_record(int K, int precision, hipEvent_t a, hipEvent_t b, int64_t sov_steps);
 vecchia_status hip_error(hipError_t e, const char* what);
 const uint64_t* device_lattice_table(int device, hipError_t* err);
+// Generators Z_j of the first n primes (n >= 1), cached per device and grown on
+// demand; the returned table stays valid until the process ends.
+const uint64_t* device_lattice_table_n(int device, int n, hipError_t* err);
 bool valid_cov(const vecchia_cov& c, std::string* why);
 bool valid_qmc(const vecchia_qmc& q, std::string* why);
 // Lattice points per QMC work item for an instance with conditioning-set size
@@ -175,6 +178,10 @@ struct vecchia_plan_s {
   // and a device buffer for their per-node results (2 x (2 + max nodes) doubles)
   std::unique_ptr<vecchia::Batch> mix1, mix2;
   double* d_mix = nullptr;
+  // workspace of vecchia_full_logcdf (covariance / Cholesky factor, limits,
+  // the points' y, partial sums), grown on demand
+  void* d_full = nullptr;
+  size_t full_bytes = 0;
   // pinned staging for vecchia_replan: {xs, ys (D doubles), perm (D int32)} x 2
   char* h_replan[2] = {nullptr, nullptr};
   hipEvent_t replan_ev[2] = {nullptr, nullptr};

@@ -36,6 +36,7 @@ EXPORTED = [
     "vecchia_plan_censored", "vecchia_plan_from_cov_censored", "vecchia_plan_censoring",
     "vecchia_mixbatch_create", "vecchia_mixbatch_logcdf", "vecchia_mixbatch_status", "vecchia_mixbatch_destroy",
     "vecchia_map_anisotropic", "vecchia_plan_block", "vecchia_plan_block_terms", "vecchia_plan_from_cov_block",
+    "vecchia_full_logcdf",
 ]
 
 
@@ -92,6 +93,7 @@ def lib():
         "vecchia_plan_block_terms": [c_void_p, POINTER(c_int64), c_void_p, c_void_p, c_void_p],
         "vecchia_plan_from_cov_block": [c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_int64, c_void_p,
                                         POINTER(c_void_p)],
+        "vecchia_full_logcdf": [c_void_p, c_void_p, c_double, c_void_p, POINTER(vecchia_qmc), c_void_p, c_void_p],
         "vecchia_replan": [c_void_p, c_void_p, c_int32, c_void_p, c_void_p],
         "vecchia_plan_info": [c_void_p, POINTER(c_int64), POINTER(c_int32)],
         "vecchia_plan_neighbours": [c_void_p, c_void_p, c_void_p],
@@ -532,4 +534,14 @@ def vecchia_plan_from_cov_block(Sigma: np.ndarray, terms, stream=None) -> int:
     _check(lib().vecchia_plan_from_cov_block(Sigma.ctypes.data, Sigma.shape[0], off.ctypes.data, var.ctypes.data,
                                              split.ctypes.data, len(terms), _stream_ptr(stream), byref(h)))
     return h.value
+
+
+def vecchia_full_logcdf(plan: int, x, qmc, out, scale: float = 1.0, cov_override=None, stream=None) -> None:
+    """Full-dimension SOV log Phi_D(x / scale) on the plan's ordering (FP64)."""
+    D, _ = vecchia_plan_info(plan)
+    q = as_qmc(qmc)
+    c = as_cov(cov_override)
+    _check(lib().vecchia_full_logcdf(plan, _dev_ptr(x, D, "x"), float(scale),
+                                     None if c is None else ctypes.addressof(c), byref(q),
+                                     _dev_ptr(out, 2, "out"), _stream_ptr(stream)))
 
