@@ -1,6 +1,6 @@
 """Benchmark of the Vecchia log-CDF hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--sections c1,c2,c3,c4,c5,mix,cens]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--sections c1,c2,c3,c4,c5,mix,cens,full]
 
 Headline workload (the JSON line's value): D = 2,500 locations uniform in
 [0,1]^2, Matern nu = 3/2 (range 0.1, nugget 1e-8), maxmin ordering, m = 10,
@@ -33,7 +33,11 @@ baseline on a bounded sample, and one object per further workload:
               replicates on 528 stations (about 356 present, 18 censored-above
               per week), anisotropic exponential model at Table 1's values,
               m = 10, 1000 x 10 points, 48 nodes per replicate, in one
-              mixture batch; FP64 on 128 replicates for the comparison.
+              mixture batch; FP64 on 128 replicates for the comparison;
+  full_dimension_comparator  the full-dimension SOV estimate against the
+              Vecchia log-CDF (m = 5, 10, 30) on 15 x 15 to 100 x 100
+              grids of unit spacing, exponential range 1 and 5, 3607 x 10
+              points (Section 3.1).
 The launch shape of each workload is set by vecchia_autotune beforehand.
 """
 from __future__ import annotations
@@ -79,7 +83,8 @@ def parse():
     ap.add_argument("--fp32-only", action="store_true",
                     help="time the full FP32 step only (short runs under a profiler)")
     ap.add_argument("--censored-T", type=int, default=1006)
-    ap.add_argument("--sections", default="c1,c2,c3,c4,c5,mix,cens",
+    ap.add_argument("--comparator-grids", type=lambda v: [int(t) for t in v.split(",")], default=[15, 30, 50, 75, 100])
+    ap.add_argument("--sections", default="c1,c2,c3,c4,c5,mix,cens,full",
                     help="comma list of workloads to run besides the headline (c2 is always run)")
     ap.add_argument("--serving-requests", type=int, default=200)
     ap.add_argument("--no-autotune", action="store_true")
@@ -185,6 +190,47 @@ def bench_mixture(V, torch, args):
     res["fp32_vs_fp64_rel"] = abs(got["fp32"][0] - got["fp64"][0]) / abs(got["fp64"][0])
     V.vecchia_plan_destroy(plan)
     return res
+
+
+def bench_comparator(V, torch, args):
+    """Full-dimension SOV (the paper's comparator, Section 3.1) against the
+    Vecchia log-CDF on the simulation study's setting: regular grids of 15 x 15
+    to 100 x 100 sites with unit spacing, exponential covariance with
+    range 1 and 5, thresholds one smooth-field draw of that scale, 3607 lattice
+    points x 10 shifts (the larger QM size of the study); Vecchia at m = 5, 10,
+    30 in FP32 and FP64. Times are per call with inputs resident."""
+    import workloads as W
+    stream = torch.cuda.Stream()
+    sp = stream.cuda_stream
+    N, R = 3607, 10
+    rows = []
+    for rho in (1.0, 5.0):
+        for n in args.comparator_grids:
+            locs = W.grid_locations(n, n) * (n - 1)
+            rng = np.random.Generator(np.random.PCG64(W.seed_for(7, n) + int(rho)))
+            xv = W.smooth_field(locs, rng, 0.5, rho)
+            cov = V.make_cov(V.VECCHIA_COV_EXPONENTIAL, 0.5, 1.0, rho, 0.0)
+            x = torch.tensor(xv, dtype=torch.float64, device="cuda")
+            out = torch.empty(2, dtype=torch.float64, device="cuda")
+            D = n * n
+            row = {"grid": f"{n}x{n}", "D": D, "range": rho}
+            plan = V.vecchia_plan(locs, V.VECCHIA_ORDER_MAXMIN, 30, cov, stream=sp)
+            q64 = V.make_qmc(N, R, 11, V.VECCHIA_FP64)
+            sec = _timed(torch, lambda: V.vecchia_full_logcdf(plan, x, q64, out, stream=sp), 1)
+            o = out.cpu().numpy()
+            row["full_sov_fp64"] = {"seconds": sec, "logF": float(o[0]), "se": float(o[1]),
+                                    "points_per_s": N * R / sec}
+            V.vecchia_plan_destroy(plan)
+            for m in (5, 10, 30):
+                p = V.vecchia_plan(locs, V.VECCHIA_ORDER_MAXMIN, m, cov, stream=sp)
+                for name, prec in (("fp32", V.VECCHIA_FP32_LOOP), ("fp64", V.VECCHIA_FP64)):
+                    q = V.make_qmc(N, R, 11, prec)
+                    sec = _timed(torch, lambda: V.vecchia_logcdf(p, x, q, out, stream=sp), 3)
+                    o = out.cpu().numpy()
+                    row[f"vecchia_m{m}_{name}"] = {"seconds": sec, "logF": float(o[0]), "se": float(o[1])}
+                V.vecchia_plan_destroy(p)
+            rows.append(row)
+    return {"workload": "exp_grids_unit_spacing_comparator", "n_points": N, "n_shifts": R, "rows": rows}
 
 
 # Section 4.1 / Table 1: range, rotation angle, aspect ratio and mixing law
@@ -546,6 +592,8 @@ def main():
         res["scale_mixture"] = bench_mixture(V, torch, args)
     if "cens" in sections:
         res["censored_likelihood"] = bench_censored(V, torch, args)
+    if "full" in sections:
+        res["full_dimension_comparator"] = bench_comparator(V, torch, args)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(inst, args.cpu_terms)
     print(json.dumps(res), flush=True)
