@@ -5,12 +5,14 @@ Bretz (2009) (Section 2.2, after eq. (6)) and does not fix the point set.
 Reading used here (all integer arithmetic, so any implementation of the same
 definition produces the same bits):
 
-* Generator: z_j = frac(sqrt(p_j)) with p_j the j-th prime (j = 0..30 for the
-  31 dimensions a term can need), held as the 64-bit fixed-point integer
+* Generator: z_j = frac(sqrt(p_j)) with p_j the j-th prime (j = 0..62 for the
+  63 dimensions a term can need), held as the 64-bit fixed-point integer
   Z_j = floor(frac(sqrt(p_j)) * 2^64) = isqrt(p_j * 2^128) mod 2^64.
 * Shift: S = SplitMix64 output number n = (term << 21) | (shift << 5) | dim of
   the stream whose state starts at `seed` (Steele, Lea & Flood 2014), i.e.
-  mix64(seed + (n + 1) * 0x9E3779B97F4A7C15 mod 2^64).
+  mix64(seed + (n + 1) * 0x9E3779B97F4A7C15 mod 2^64), for dim < 32; dimensions
+  32..62 (terms of more than 32 variables) use n = 2^62 + (term << 22) +
+  (shift << 6) + dim, a range the first form never reaches.
 * Point p = 1..N of shift r in dimension j: U = (p * Z_j + S) mod 2^64.
 * Baker (tent) transform: W = |2U - 2^64| (W = 2^64 saturates to 2^64 - 1).
 * FP64 coordinate: the midpoint of the 2^-52 cell holding W / 2^64,
@@ -27,7 +29,7 @@ import numpy as np
 
 MASK64 = (1 << 64) - 1
 GOLDEN_GAMMA = 0x9E3779B97F4A7C15
-MAX_DIMS = 31
+MAX_DIMS = 63
 MAX_SHIFTS = 1 << 16
 
 
@@ -62,8 +64,10 @@ def splitmix64_output(seed: int, n: int) -> int:
 
 def shift(seed: int, term: int, r: int, dim: int) -> int:
     """Random shift of dimension `dim` in replicate `r` of plan-order term `term`."""
-    assert 0 <= r < MAX_SHIFTS and 0 <= dim < 32 and term >= 0
-    return splitmix64_output(seed, (term << 21) | (r << 5) | dim)
+    assert 0 <= r < MAX_SHIFTS and 0 <= dim < 64 and term >= 0
+    if dim < 32:
+        return splitmix64_output(seed, (term << 21) | (r << 5) | dim)
+    return splitmix64_output(seed, (1 << 62) | (term << 22) | (r << 6) | dim)
 
 
 def full_shift(seed: int, r: int, dim: int) -> int:

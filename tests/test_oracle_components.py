@@ -37,12 +37,13 @@ def test_first_primes_table():
 
 def test_richtmyer_generator_is_frac_sqrt_prime():
     Z = lattice.richtmyer_generator()
-    for p, z in zip(lattice.first_primes(31), Z):
+    assert len(Z) == 63 and lattice.first_primes(63)[-1] == 307   # the 63rd prime
+    for p, z in zip(lattice.first_primes(63), Z):
         ip = math.isqrt(p)
         full = (ip << 64) + z                      # floor(sqrt(p) * 2^64)
         assert full * full <= p << 128 < (full + 1) * (full + 1)
-        assert abs(z / 2.0 ** 64 - (math.sqrt(p) - ip)) < 1e-15
-    assert len(set(Z)) == 31
+        assert abs(z / 2.0 ** 64 - (math.sqrt(p) - ip)) <= 2 * math.ulp(math.sqrt(p))
+    assert len(set(Z)) == 63
 
 
 def test_baker_transform_edges_and_symmetry():
@@ -95,9 +96,12 @@ def test_shift_keys_are_distinct():
     seen = set()
     for term in range(4):
         for r in range(3):
-            for d in range(31):
+            for d in range(63):
                 seen.add(lattice.shift(99, term, r, d))
-    assert len(seen) == 4 * 3 * 31
+    assert len(seen) == 4 * 3 * 63
+    # the two key forms as stated
+    assert lattice.shift(7, 5, 2, 31) == lattice.splitmix64_output(7, (5 << 21) | (2 << 5) | 31)
+    assert lattice.shift(7, 5, 2, 32) == lattice.splitmix64_output(7, (1 << 62) | (5 << 22) | (2 << 6) | 32)
 
 
 # ------------------------------------------------------------- covariance ---
