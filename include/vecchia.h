@@ -69,7 +69,7 @@ enum { VECCHIA_COV_EXPONENTIAL = 0, VECCHIA_COV_MATERN = 1 };
  * precision; covariance, Cholesky, per-term means and the sum in double. */
 enum { VECCHIA_FP64 = 0, VECCHIA_FP32_LOOP = 1 };
 
-#define VECCHIA_MAX_M 31          /* conditioning-set size limit (term dimension <= 32) */
+#define VECCHIA_MAX_M 63          /* conditioning-set size limit (term dimension <= 64) */
 #define VECCHIA_MAX_SHIFTS 65536
 #define VECCHIA_MAX_POINTS 1073741824
 #define VECCHIA_MIX_SEARCH_NODES 24   /* search points of the scale-mixture rule */
@@ -128,7 +128,7 @@ vecchia_status vecchia_map_anisotropic(const double* locs_host, int64_t D, doubl
  * locs_host: D x dim row-major, dim must be 2. cov: default covariance; family
  * and nu are fixed for the plan, sigma2/range/nugget may be overridden per
  * call. Synchronises hip_stream before returning.
- * Errors: INVALID (D < 1, D >= 2^31, dim != 2, m outside 0..31, bad ordering,
+ * Errors: INVALID (D < 1, D >= 2^31, dim != 2, m outside 0..63, bad ordering,
  * permutation or covariance, non-finite locations), NOMEM, HIP. */
 vecchia_status vecchia_plan(const double* locs_host, int64_t D, int32_t dim, int32_t ordering,
                             const int64_t* perm_in_host, int32_t m, const vecchia_cov* cov,

@@ -270,7 +270,7 @@ vecchia_status check_plan_args(int32_t dim, int32_t m, const vecchia_cov* cov, v
   if (!out || !cov) return set_error(VECCHIA_E_INVALID, "null pointer");
   *out = nullptr;
   if (dim != 2) return set_error(VECCHIA_E_INVALID, "only 2-D locations are supported (dim must be 2)");
-  if (m < 0 || m > VECCHIA_MAX_M) return set_error(VECCHIA_E_INVALID, "m must be in 0..31");
+  if (m < 0 || m > VECCHIA_MAX_M) return set_error(VECCHIA_E_INVALID, "m must be in 0..63");
   std::string why;
   if (!valid_cov(*cov, &why)) return set_error(VECCHIA_E_INVALID, why);
   return VECCHIA_OK;
@@ -318,7 +318,7 @@ static vecchia_status plan_from_cov_impl(const double* cov_host, int64_t D, cons
   *out = nullptr;
   if (D < 1 || D > 4096) return set_error(VECCHIA_E_INVALID, "D must be in 1..4096");
   if (n_obs < 0 || n_obs > D) return set_error(VECCHIA_E_INVALID, "n_observed must be in 0..D");
-  if (m < 0 || m > VECCHIA_MAX_M) return set_error(VECCHIA_E_INVALID, "m must be in 0..31");
+  if (m < 0 || m > VECCHIA_MAX_M) return set_error(VECCHIA_E_INVALID, "m must be in 0..63");
   for (int64_t a = 0; a < D; ++a)
     for (int64_t b = 0; b < D; ++b) {
       const double v = cov_host[a * D + b];
@@ -396,7 +396,7 @@ vecchia_status vecchia_plan_block(const double* locs_host, int64_t D, int32_t di
   vecchia_status st = check_plan_args(dim, m, cov, out);
   if (st != VECCHIA_OK) return st;
   if (p < 1 || (int64_t)p * (m + 1) > kMaxVars)
-    return set_error(VECCHIA_E_INVALID, "groups need 1 <= p and p (m + 1) <= 32 variables per term");
+    return set_error(VECCHIA_E_INVALID, "groups need 1 <= p and p (m + 1) <= 64 variables per term");
   std::vector<int64_t> perm(D > 0 && D <= 0x7fffffffLL ? D : 0);
   st = order_impl(locs_host, D, ordering, perm_in_host, perm.data());
   if (st != VECCHIA_OK) return st;
@@ -432,7 +432,7 @@ vecchia_status vecchia_plan_from_cov_block(const double* cov_host, int64_t D, co
   int nv_max = 0;
   for (int64_t g = 0; g < n_terms; ++g) {
     const int nv = var_off_host[g + 1] - var_off_host[g];
-    if (nv < 1 || nv > kMaxVars) return set_error(VECCHIA_E_INVALID, "every term needs 1..32 variables");
+    if (nv < 1 || nv > kMaxVars) return set_error(VECCHIA_E_INVALID, "every term needs 1..64 variables");
     if (split_host[g] < 0 || split_host[g] >= nv)
       return set_error(VECCHIA_E_INVALID, "split must be in 0..(variables - 1)");
     for (int c = 0; c < nv; ++c) {

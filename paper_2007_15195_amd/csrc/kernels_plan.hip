@@ -26,7 +26,7 @@ __global__ __launch_bounds__(64 * kKnnWaves) void knn_preceding(const double* __
                                                                 const double* __restrict__ ys, int64_t D,
                                                                 int32_t* __restrict__ nbr,
                                                                 int32_t* __restrict__ kcnt, int64_t q_base,
-                                                                int64_t q_end, int group) {
+                                                                int64_t q_end, int group, int m) {
 #pragma clang fp contract(off)
   __shared__ double2 tile[kKnnTile];
   const int lane = threadIdx.x & 63;
@@ -76,7 +76,7 @@ __global__ __launch_bounds__(64 * kKnnWaves) void knn_preceding(const double* __
     }
   }
   if (!valid) return;
-  const int k = (int)(lim_i < M ? lim_i : M);
+  const int k = (int)(lim_i < m ? lim_i : m);   // m <= M: the list keeps the M best
   int mine = -1;   // lane s keeps the s-th neighbour
   for (int s = 0; s < k; ++s) {
     double d = bd[0];
@@ -100,7 +100,7 @@ __global__ __launch_bounds__(64 * kKnnWaves) void knn_preceding(const double* __
       bj[M - 1] = -1;
     }
   }
-  if (lane < M) nbr[i * M + lane] = lane < k ? mine : -1;
+  if (lane < m) nbr[i * m + lane] = lane < k ? mine : -1;
   if (lane == 0) kcnt[i] = k;
 }
 
@@ -160,14 +160,14 @@ __global__ __launch_bounds__(256) void grid_scatter(const double* __restrict__ x
 template <int M>
 __global__ __launch_bounds__(256) void knn_grid(const double* __restrict__ xs, const double* __restrict__ ys,
                                                 int64_t D, KnnGrid g, int32_t* __restrict__ nbr,
-                                                int32_t* __restrict__ kcnt, int64_t q_base) {
+                                                int32_t* __restrict__ kcnt, int64_t q_base, int m) {
 #pragma clang fp contract(off)
   const int64_t i = q_base + (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= D) return;
-  const int k = (int)(i < M ? i : M);
+  const int k = (int)(i < m ? i : m);   // m <= M: the list keeps the M best
   kcnt[i] = k;
   if (k == 0) {
-    for (int s = 0; s < M; ++s) nbr[i * M + s] = -1;
+    for (int s = 0; s < m; ++s) nbr[i * m + s] = -1;
     return;
   }
   const double qx = xs[i], qy = ys[i];
@@ -233,7 +233,8 @@ __global__ __launch_bounds__(256) void knn_grid(const double* __restrict__ xs, c
     }
   }
 #pragma unroll
-  for (int s = 0; s < M; ++s) nbr[i * M + s] = s < k ? bj[s] : -1;
+  for (int s = 0; s < M; ++s)
+    if (s < m) nbr[i * m + s] = s < k ? bj[s] : -1;
 }
 
 __global__ void fill_i64(int64_t* p, int64_t n, int64_t v) {
@@ -248,7 +249,7 @@ __global__ void fill_i32(int32_t* p, int64_t n, int32_t v) {
 
 template <int M>
 hipError_t knn_dispatch(const double* xs, const double* ys, int64_t D, int32_t* nbr, int32_t* kcnt,
-                        const KnnGrid* grid, int group, hipStream_t s) {
+                        const KnnGrid* grid, int group, int m, hipStream_t s) {
   // queries below q_split scan their i preceding points with a wave each; the
   // rest (large plans only) search the grid, where preceding points are dense
   const int64_t q_split = grid ? (D < kKnnGridMinD ? D : kKnnGridMinD) : D;
@@ -257,7 +258,7 @@ hipError_t knn_dispatch(const double* xs, const double* ys, int64_t D, int32_t* 
     for (int64_t b = q_split; b < D; b += kPer) {
       const int64_t n = D - b < kPer ? D - b : kPer;
       hipLaunchKernelGGL(knn_grid<M>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, xs, ys, D, *grid, nbr,
-                         kcnt, b);
+                         kcnt, b, m);
       const hipError_t e = hipGetLastError();
       if (e != hipSuccess) return e;
     }
@@ -267,7 +268,7 @@ hipError_t knn_dispatch(const double* xs, const double* ys, int64_t D, int32_t* 
     const int64_t n = q_split - b < kPerWave ? q_split - b : kPerWave;
     const unsigned blocks = (unsigned)((n + kKnnWaves - 1) / kKnnWaves);
     hipLaunchKernelGGL(knn_preceding<M>, dim3(blocks), dim3(64 * kKnnWaves), 0, s, xs, ys, D, nbr, kcnt, b,
-                       q_split, group);
+                       q_split, group, m);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -279,7 +280,7 @@ hipError_t knn_switch(int m, const double* xs, const double* ys, int64_t D, int3
                       int32_t* kcnt, const KnnGrid* grid, int group, hipStream_t s,
                       std::integer_sequence<int, Ms...>) {
   hipError_t err = hipErrorInvalidValue;
-  ((m == Ms + 1 ? (err = knn_dispatch<Ms + 1>(xs, ys, D, nbr, kcnt, grid, group, s), 0) : 0), ...);
+  ((m == Ms + 1 ? (err = knn_dispatch<Ms + 1>(xs, ys, D, nbr, kcnt, grid, group, m, s), 0) : 0), ...);
   return err;
 }
 
@@ -325,7 +326,13 @@ hipError_t launch_knn(const double* xs, const double* ys, int64_t D, int m, int3
     const hipError_t e = build_grid(xs, ys, D, *grid, s);
     if (e != hipSuccess) return e;
   }
-  return knn_switch(m, xs, ys, D, nbr, kcnt, grid, group, s, std::make_integer_sequence<int, kMaxM>{});
+  if (m <= kMaxUnrolledK)
+    return knn_switch(m, xs, ys, D, nbr, kcnt, grid, group, s, std::make_integer_sequence<int, kMaxUnrolledK>{});
+  // larger sets: lists of capacity 40, 48, 56 or 64 holding the m wanted
+  if (m <= 40) return knn_dispatch<40>(xs, ys, D, nbr, kcnt, grid, group, m, s);
+  if (m <= 48) return knn_dispatch<48>(xs, ys, D, nbr, kcnt, grid, group, m, s);
+  if (m <= 56) return knn_dispatch<56>(xs, ys, D, nbr, kcnt, grid, group, m, s);
+  return knn_dispatch<64>(xs, ys, D, nbr, kcnt, grid, group, m, s);
 }
 
 }  // namespace vecchia

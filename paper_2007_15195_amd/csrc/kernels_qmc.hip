@@ -295,6 +295,223 @@ __device__ __forceinline__ void item_f32(const Item& it, const Aux32* __restrict
   }
 }
 
+// ---------------------------------------------------------------------------
+// Chains of kMaxUnrolledK + 1 .. kMaxM steps (terms of 33..64 variables): the
+// same recursions with a runtime K, not unrolled. Each lane's y live in LDS
+// (column `lane` of ys, so the lanes' accesses never share a bank), the rows
+// and the K shifts are staged in LDS once per work item, and U_j = p Z_j + S_j
+// is formed from the point index in each step. One wave per block.
+constexpr int kGenRowElems = (kMaxM + 1) * (kMaxM + 2) / 2;
+
+__device__ __forceinline__ void item_f32_gen(const Item& it, const Aux32* __restrict__ aux32,
+                                             const uint64_t* __restrict__ Zg, double* __restrict__ sums) {
+  __shared__ float srow[kGenRowElems];
+  __shared__ float ys[kMaxM][64];
+  __shared__ uint64_t sh[kMaxM];
+  const InstDesc& I = *it.I;
+  const int lane = threadIdx.x & 63;
+  const int K = it.K;
+  const bool block = I.split != nullptr;
+  const int sp = block ? uniform(I.split[it.i]) : K;
+  const float* __restrict__ prep = reinterpret_cast<const float*>(I.prep) + it.i * I.prep_stride;
+  const Aux32 ax = aux32[it.t];
+  const bool split0 = uniform(ax.en0 != 0.0f) != 0;
+  const int p_begin = 1 + it.c * I.chunk_points;
+  const int p_last = min(I.n_points, p_begin + I.chunk_points - 1);
+  const int rows = (K + 1) * (K + 2) / 2;
+  for (int e = lane; e < rows; e += 64) srow[e] = prep[e];
+  for (int j = lane; j < K; j += 64) sh[j] = lattice_shift(I.seed, it.i, it.r, j);
+  __syncthreads();
+  double acc_num = 0.0, acc_den = 0.0, acc_cnum = 0.0;
+  for (int p0 = p_begin; p0 <= p_last; p0 += 64) {
+    const uint64_t pt = (uint64_t)(p0 + lane);
+    float em = ax.em0, en = ax.en0, m = ax.ec0;
+    bool neg = ax.neg0 != 0.0f;
+    bool split = split0;
+    float qm = 1.0f;
+    int qe = 0;
+    float dm = 1.0f;
+    int de = 0;
+    float cc = 0.0f;
+    if (block) {
+      qe = (int)ax.en0 + __builtin_amdgcn_frexp_expf(ax.em0);
+      qm = __builtin_amdgcn_frexp_mantf(ax.em0);
+      if (sp == 0) cc = ax.ec0;
+    }
+#pragma unroll 1
+    for (int a = 1; a <= K; ++a) {
+      if (block && a == sp) {
+        dm = qm;
+        de = qe;
+      }
+      const int ro = a * (a + 1) / 2;
+      const CoordF32 wp = lattice_coord_f32((uint32_t)((pt * Zg[a - 1] + sh[a - 1]) >> 32));
+      const float um = wp.w * em;
+      const bool lower = neg || um <= 0.5f;
+      const float qt = lower ? um : fmaf(wp.w, m, wp.wc);
+      const float lq = fast_log2(qt);
+      float z = ninv_tail_from_log2(lq);
+      if (__builtin_expect(split, 0)) {
+        z = ninv_tail_from_log2(lq + en);
+        en = 0.0f;
+        split = false;
+      }
+      ys[a - 1][lane] = lower ? -z : z;
+      float v = srow[ro + a];
+      int c = 0;
+      for (; c + 4 <= a; c += 4) {
+        v = fmaf(-srow[ro + c], ys[c][lane], v);
+        v = fmaf(-srow[ro + c + 1], ys[c + 1][lane], v);
+        v = fmaf(-srow[ro + c + 2], ys[c + 2][lane], v);
+        v = fmaf(-srow[ro + c + 3], ys[c + 3][lane], v);
+      }
+      for (; c < a; ++c) v = fmaf(-srow[ro + c], ys[c][lane], v);
+      const PhiParts ph = phi_f32(v);
+      em = ph.em;
+      m = ph.m;
+      neg = ph.neg;
+      if (__builtin_expect(__builtin_amdgcn_fcmpf(v, -kDeepV, 4) != 0, 0)) {
+        if (v < -kDeepV) {
+          const float fl = floorf(fmaxf(ph.f, -1048576.0f));
+          em = fast_exp2(fmaxf(ph.f, -1048576.0f) - fl) * ph.R;
+          en = fl;
+          if (block || a < K) qe += (int)fl;
+        }
+        split = true;
+      }
+      if (block && a >= sp) {
+        const float eca = neg ? 1.0f - ldexpf(em, (int)en) : m;
+        cc = fmaf(eca, 1.0f - cc, cc);
+      }
+      if (block || a < K) {
+        qm *= em;
+        const bool low = qm < 0x1p-50f;
+        if (__builtin_expect(any_lane(low), 0)) {
+          if (low) {
+            qe += __builtin_amdgcn_frexp_expf(qm);
+            qm = __builtin_amdgcn_frexp_mantf(qm);
+          }
+        }
+      }
+    }
+    const bool in_chunk = p0 + lane <= p_last;
+    if (block) {
+      const double den = ldexp((double)(in_chunk ? dm : 0.0f), de);
+      acc_den += den;
+      acc_num += ldexp((double)(in_chunk ? qm : 0.0f), qe);
+      acc_cnum = fma(den, (double)cc, acc_cnum);
+    } else {
+      const float qml = in_chunk ? qm : 0.0f;
+      const int enk = (int)en;
+      const double den = ldexp((double)qml, qe);
+      const double num = ldexp(den * (double)em, enk);
+      const float ec = neg ? 1.0f - ldexpf(em, enk) : m;
+      acc_den += den;
+      acc_num += num;
+      acc_cnum = fma(den, (double)ec, acc_cnum);
+    }
+  }
+  acc_num = wave_sum(acc_num);
+  acc_den = wave_sum(acc_den);
+  acc_cnum = wave_sum(acc_cnum);
+  if (lane == 0) {
+    double* o = item_out(I, it, sums);
+    o[0] = acc_num;
+    o[1] = acc_den;
+    o[2] = acc_cnum;
+  }
+}
+
+__device__ __forceinline__ void item_f64_gen(const Item& it, const Aux64* __restrict__ aux64,
+                                             const uint64_t* __restrict__ Zg, double* __restrict__ sums) {
+  __shared__ double srow[kGenRowElems];
+  __shared__ double ys[kMaxM][64];
+  __shared__ uint64_t sh[kMaxM];
+  const InstDesc& I = *it.I;
+  const int lane = threadIdx.x & 63;
+  const int K = it.K;
+  const bool block = I.split != nullptr;
+  const int sp = block ? uniform(I.split[it.i]) : K;
+  const double* __restrict__ prep = reinterpret_cast<const double*>(I.prep) + it.i * I.prep_stride;
+  const double e0 = aux64[it.t].e0;
+  const int p_begin = 1 + it.c * I.chunk_points;
+  const int p_last = min(I.n_points, p_begin + I.chunk_points - 1);
+  const int rows = (K + 1) * (K + 2) / 2;
+  for (int e = lane; e < rows; e += 64) srow[e] = prep[e];
+  for (int j = lane; j < K; j += 64) sh[j] = lattice_shift(I.seed, it.i, it.r, j);
+  __syncthreads();
+  double acc_num = 0.0, acc_den = 0.0;
+  for (int p0 = p_begin; p0 <= p_last; p0 += 64) {
+    const uint64_t pt = (uint64_t)(p0 + lane);
+    const bool live = p0 + lane <= p_last;
+    double e = e0, prod = e0, head = 1.0;
+    bool alive = e0 > 0.0;
+#pragma unroll 1
+    for (int a = 1; a <= K; ++a) {
+      if (block && a == sp) head = prod;
+      const double w = lattice_coord_f64(pt * Zg[a - 1] + sh[a - 1]);
+      const double u = fmax(w * e, 2.2250738585072014e-308);
+      ys[a - 1][lane] = alive ? ncdfinv64(u) : 0.0;
+      const double* row = srow + a * (a + 1) / 2;
+      double acc = row[a];
+      for (int c = 0; c < a; ++c) acc -= row[c] * ys[c][lane];
+      e = alive ? ncdf64(acc) : 0.0;
+      alive = alive && e > 0.0;
+      if (block || a < K) prod *= e;
+    }
+    if (live) {
+      if (block) {
+        acc_den += head;
+        acc_num += prod;
+      } else {
+        acc_den += prod;
+        acc_num += prod * e;
+      }
+    }
+  }
+  acc_num = wave_sum(acc_num);
+  acc_den = wave_sum(acc_den);
+  if (lane == 0) {
+    double* o = item_out(I, it, sums);
+    o[0] = acc_num;
+    o[1] = acc_den;
+    o[2] = -1.0;
+  }
+}
+
+__global__ __launch_bounds__(64) void qmc_gen_f32(const InstDesc* __restrict__ insts,
+                                                  const RangeDesc* __restrict__ ranges, int n_ranges,
+                                                  const Aux32* __restrict__ aux32, const uint64_t* __restrict__ Zg,
+                                                  double* __restrict__ sums, int64_t item_base) {
+  const Item it = decode_item(insts, ranges, n_ranges, item_base + (int64_t)blockIdx.x);
+  item_f32_gen(it, aux32, Zg, sums);
+}
+
+__global__ __launch_bounds__(64) void qmc_gen_f64(const InstDesc* __restrict__ insts,
+                                                  const RangeDesc* __restrict__ ranges, int n_ranges,
+                                                  const Aux64* __restrict__ aux64, const uint64_t* __restrict__ Zg,
+                                                  double* __restrict__ sums, int64_t item_base) {
+  const Item it = decode_item(insts, ranges, n_ranges, item_base + (int64_t)blockIdx.x);
+  item_f64_gen(it, aux64, Zg, sums);
+}
+
+hipError_t qmc_gen_dispatch(int precision, const InstDesc* insts, const RangeDesc* ranges, int n_ranges,
+                            int64_t n_items, const Aux64* aux64, const Aux32* aux32, const uint64_t* Z,
+                            double* sums, hipStream_t s) {
+  if (n_items > 0x7fffffffLL) return hipErrorInvalidValue;
+  constexpr int64_t kPer = kMaxLaunchThreads / 64;   // items (one wave each) per launch
+  for (int64_t b = 0; b < n_items; b += kPer) {
+    const unsigned n = (unsigned)(n_items - b < kPer ? n_items - b : kPer);
+    if (precision == VECCHIA_FP32_LOOP)
+      hipLaunchKernelGGL(qmc_gen_f32, dim3(n), dim3(64), 0, s, insts, ranges, n_ranges, aux32, Z, sums, b);
+    else
+      hipLaunchKernelGGL(qmc_gen_f64, dim3(n), dim3(64), 0, s, insts, ranges, n_ranges, aux64, Z, sums, b);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 // Minimum waves per SIMD requested per chain size K: the largest value at which
 // the unrolled chain still compiles without spilling (measured on gfx950; the
 // hint only caps registers, so chains that fit more waves keep them).
@@ -357,11 +574,13 @@ hipError_t launch_qmc(int K, int precision, bool block, const InstDesc* d_insts,
                       const uint64_t* d_Z, double* sums, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
   if (K < 1 || K > kMaxM) return hipErrorInvalidValue;
+  if (K > kMaxUnrolledK)
+    return qmc_gen_dispatch(precision, d_insts, d_ranges, n_ranges, n_items, aux64, aux32, d_Z, sums, s);
   if (block)
     return qmc_switch<true>(K, precision, d_insts, d_ranges, n_ranges, n_items, aux64, aux32, d_Z, sums, s,
-                            std::make_integer_sequence<int, kMaxM>{});
+                            std::make_integer_sequence<int, kMaxUnrolledK>{});
   return qmc_switch<false>(K, precision, d_insts, d_ranges, n_ranges, n_items, aux64, aux32, d_Z, sums, s,
-                           std::make_integer_sequence<int, kMaxM>{});
+                           std::make_integer_sequence<int, kMaxUnrolledK>{});
 }
 
 }  // namespace vecchia

@@ -3,8 +3,8 @@
 // Generator z_j = frac(sqrt(p_j)), p_j the j-th prime, held as the 64-bit
 // fixed-point integer Z_j (computed on the host by an exact integer square
 // root and passed to the kernels). Shift S = SplitMix64 output number
-// n = (term << 21) | (shift << 5) | dim of the stream seeded with the call's
-// seed (Steele, Lea & Flood 2014). Point p: U = p Z_j + S mod 2^64; baker
+// n = (term << 21) | (shift << 5) | dim (dim < 32) of the stream seeded with
+// the call's seed (Steele, Lea & Flood 2014). Point p: U = p Z_j + S mod 2^64; baker
 // transform W = |2U - 2^64| (2^64 saturates); the coordinate is the midpoint
 // of W's cell on the 2^-52 grid (FP64) or, from U's upper half, on the 2^-23
 // grid (FP32).
@@ -22,8 +22,11 @@ __device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t n) {
   return z ^ (z >> 31);
 }
 
+// Dimensions 32..62 (terms of more than 32 variables) take the key
+// 2^62 + (term << 22) + (shift << 6) + dim, a range the first form never reaches.
 __device__ __forceinline__ uint64_t lattice_shift(uint64_t seed, int64_t term, int r, int dim) {
-  return splitmix64(seed, ((uint64_t)term << 21) | ((uint64_t)r << 5) | (uint64_t)dim);
+  if (dim < 32) return splitmix64(seed, ((uint64_t)term << 21) | ((uint64_t)r << 5) | (uint64_t)dim);
+  return splitmix64(seed, (1ULL << 62) | ((uint64_t)term << 22) | ((uint64_t)r << 6) | (uint64_t)dim);
 }
 
 // FP64 coordinate (2 floor(W / 2^12) + 1) 2^-53.

@@ -10,6 +10,9 @@ namespace vecchia {
 
 constexpr int kMaxM = VECCHIA_MAX_M;   // conditioning-set size limit
 constexpr int kMaxVars = kMaxM + 1;    // variables per term
+// Chains of up to this many steps run fully unrolled with y in registers;
+// longer ones (up to kMaxM) run in the general kernel with y in LDS.
+constexpr int kMaxUnrolledK = 31;
 constexpr int kFinalizeThreads = 256;
 // A launch may hold fewer than 2^32 work-items in total; per-term and per-item
 // kernels are split into launches of at most this many threads.

@@ -79,7 +79,7 @@ def test_given_ordering_and_validation():
 def test_plan_rejects_bad_arguments_before_gpu_work():
     locs = np.random.default_rng(1).random((5, 2))
     cov = V.make_cov(V.VECCHIA_COV_MATERN, 1.5, 1.0, 0.1, 0.0)
-    for kwargs in (dict(m=32), dict(m=-1)):
+    for kwargs in (dict(m=64), dict(m=-1)):
         with pytest.raises(V.VecchiaError) as e:
             V.vecchia_plan(locs, W.ORDER_COORD, kwargs["m"], cov, stream=0)
         assert e.value.status == 1
@@ -122,13 +122,13 @@ def test_tuning_table_and_autotune_validation():
     finally:
         V.vecchia_tuning_set(V.VECCHIA_FP32_LOOP, 10, 0)
     assert V.vecchia_tuning_get(V.VECCHIA_FP32_LOOP, 10) == 0
-    for bad in ((2, 10, 1024), (1, 32, 1024), (1, -1, 1024), (1, 10, 100), (1, 10, 32), (1, 10, 1 << 25)):
+    for bad in ((2, 10, 1024), (1, 64, 1024), (1, -1, 1024), (1, 10, 100), (1, 10, 32), (1, 10, 1 << 25)):
         with pytest.raises(V.VecchiaError) as e:
             V.vecchia_tuning_set(*bad)
         assert e.value.status == 1
     # the autotuner rejects bad arguments before any device work
     for bad in ((2, 1000, 4, [3]), (1, 0, 4, [3]), (1, 1000, 0, [3]), (1, 1000, 4, []), (1, 1000, 4, [0]),
-                (1, 1000, 4, [5, 32])):
+                (1, 1000, 4, [5, 64])):
         with pytest.raises(V.VecchiaError) as e:
             V.vecchia_autotune(*bad, stream=0)
         assert e.value.status == 1
@@ -249,7 +249,7 @@ def test_mahalanobis_special_cases():
 def test_block_plan_arguments_rejected_on_the_host():
     locs = np.random.default_rng(1).random((20, 2))
     cov = V.make_cov(V.VECCHIA_COV_MATERN, 1.5, 1.0, 0.1, 0.0)
-    for m, p in ((10, 3), (4, 7), (1, 0), (0, 33)):
+    for m, p in ((10, 6), (4, 13), (1, 0), (0, 65)):
         with pytest.raises(V.VecchiaError) as e:
             V.vecchia_plan_block(locs, W.ORDER_COORD, m, p, cov, stream=0)
         assert e.value.status == 1

@@ -49,7 +49,7 @@ def test_block_terms_match_the_oracle(D, m, p, order):
         assert np.array_equal(v, np.concatenate([C, G])), g
 
 
-@pytest.mark.parametrize("m,p", [(4, 3), (5, 5), (2, 8)])
+@pytest.mark.parametrize("m,p", [(4, 3), (5, 5), (2, 8), (15, 4)])
 def test_fp64_block_logcdf_matches_the_oracle(m, p):
     torch = torch_cuda()
     from paper_2007_15195_amd import vecchia as V

@@ -34,7 +34,8 @@ def _compare_fp64(g, o, idx_user=None):
 
 # ------------------------------------------------------------------ plan ---
 
-@pytest.mark.parametrize("case", ["grid20_m5", "uniform2500_m10", "dupes_m7", "uniform_m31", "tiny"])
+@pytest.mark.parametrize("case", ["grid20_m5", "uniform2500_m10", "dupes_m7", "uniform_m31", "tiny",
+                                  "uniform_m50", "grid_m63"])
 def test_neighbours_and_order_match_oracle(case):
     torch_cuda()
     from paper_2007_15195_amd import vecchia as V
@@ -48,6 +49,11 @@ def test_neighbours_and_order_match_oracle(case):
         inst.locs = np.round(inst.locs * 8) / 8.0
     elif case == "uniform_m31":
         inst = W.small_random_instance(700, 31, 6)
+    elif case == "uniform_m50":              # lists of capacity 56 holding 50
+        inst = W.small_random_instance(900, 50, 8)
+    elif case == "grid_m63":                 # the largest m, ties on a lattice
+        inst = W.grid400_exponential()
+        inst.m = 63
     else:
         inst = W.small_random_instance(3, 31, 7)
     plan = V.vecchia_plan(inst.locs, inst.ordering, inst.m, inst.cov)
@@ -61,7 +67,7 @@ def test_neighbours_and_order_match_oracle(case):
 
 
 @pytest.mark.parametrize("case", ["uniform40k_maxmin_m10", "lattice_coord_m8", "repeated_given_m15",
-                                  "thin_strip_coord_m20", "uniform20k_maxmin_m31"])
+                                  "thin_strip_coord_m20", "uniform20k_maxmin_m31", "uniform20k_coord_m45"])
 def test_grid_neighbour_search_matches_oracle(case):
     # plans above the grid threshold (16,384 points) search through the cell grid;
     # sampled rows (every k < m row, the last row and random rows) must equal the
@@ -83,6 +89,8 @@ def test_grid_neighbour_search_matches_oracle(case):
     elif case == "thin_strip_coord_m20":      # a strip far from the origin
         locs = rng.random((20_000, 2)) * np.array([1e-6, 1.0]) + 1e3
         order, m = W.ORDER_COORD, 20
+    elif case == "uniform20k_coord_m45":
+        locs, order, m = rng.random((20_000, 2)), W.ORDER_COORD, 45
     else:
         locs, order, m = rng.random((20_000, 2)), W.ORDER_MAXMIN, 31
     D = locs.shape[0]
@@ -114,7 +122,10 @@ def test_fp64_grid400_full_parity():
 @pytest.mark.parametrize("D,m,N,R,nu,seed", [
     (37, 3, 100, 3, 1.5, 1),      # N not a multiple of 64 (ragged tail of lanes)
     (90, 10, 1, 2, 2.5, 2),       # a single lattice point
-    (64, 31, 200, 2, 0.5, 3),     # the maximum conditioning-set size
+    (64, 31, 200, 2, 0.5, 3),     # the longest unrolled chain
+    (80, 32, 130, 2, 1.5, 7),     # the shortest chain of the general kernel
+    (120, 50, 300, 3, 1.5, 8),    # m = 50, as in the simulation study
+    (90, 63, 200, 2, 0.5, 9),     # the maximum conditioning-set size
     (1, 5, 64, 4, 1.5, 4),        # one location: exact term only
     (50, 0, 64, 2, 1.5, 5),       # m = 0: independence, every term exact
     (129, 2, 65, 1, 1.5, 6),      # one shift: SE is NaN
@@ -246,3 +257,17 @@ def test_not_positive_definite_is_reported():
     assert "term 2" in V.vecchia_last_error()
     assert math.isnan(out.cpu().numpy()[0])
     V.vecchia_plan_destroy(plan)
+
+
+def test_fp32_general_kernel_against_fp64():
+    # chains of 33..64 variables in both precisions (the general kernel), FP32
+    # within the stated tolerance of FP64 on the same points
+    for m, seed in ((40, 61), (63, 62)):
+        inst = W.small_random_instance(300, m, seed, n_points=1000, n_shifts=4, rho=0.1)
+        g32 = gpu_run(inst, precision=W.PREC_FP32)
+        g64 = gpu_run(inst, precision=W.PREC_FP64)
+        d = np.abs(g32["terms"][:, 0] - g64["terms"][:, 0])
+        print("m", m, "fp32", g32["out"], "fp64", g64["out"], "max term diff", d.max(), flush=True)
+        assert d.max() <= FP32_TERM_TOL
+        assert abs(g32["out"][0] - g64["out"][0]) <= 1e-2 * abs(g64["out"][0])
+
