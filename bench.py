@@ -35,7 +35,7 @@ baseline on a bounded sample, and one object per further workload:
               m = 10, 1000 x 10 points, 48 nodes per replicate, in one
               mixture batch; FP64 on 128 replicates for the comparison;
   full_dimension_comparator  the full-dimension SOV estimate against the
-              Vecchia log-CDF (m = 5, 10, 30) on 15 x 15 to 100 x 100
+              Vecchia log-CDF (m = 5, 10, 30, 50) on 15 x 15 to 100 x 100
               grids of unit spacing, exponential range 1 and 5, 3607 x 10
               points (Section 3.1).
 The launch shape of each workload is set by vecchia_autotune beforehand.
@@ -198,7 +198,7 @@ def bench_comparator(V, torch, args):
     to 100 x 100 sites with unit spacing, exponential covariance with
     range 1 and 5, thresholds one smooth-field draw of that scale, 3607 lattice
     points x 10 shifts (the larger QM size of the study); Vecchia at m = 5, 10,
-    30 in FP32 and FP64. Times are per call with inputs resident."""
+    30 and 50 in FP32 and FP64. Times are per call with inputs resident."""
     import workloads as W
     stream = torch.cuda.Stream()
     sp = stream.cuda_stream
@@ -221,7 +221,7 @@ def bench_comparator(V, torch, args):
             row["full_sov_fp64"] = {"seconds": sec, "logF": float(o[0]), "se": float(o[1]),
                                     "points_per_s": N * R / sec}
             V.vecchia_plan_destroy(plan)
-            for m in (5, 10, 30):
+            for m in (5, 10, 30, 50):
                 p = V.vecchia_plan(locs, V.VECCHIA_ORDER_MAXMIN, m, cov, stream=sp)
                 for name, prec in (("fp32", V.VECCHIA_FP32_LOOP), ("fp64", V.VECCHIA_FP64)):
                     q = V.make_qmc(N, R, 11, prec)
