@@ -515,7 +515,7 @@ hipError_t qmc_gen_dispatch(int precision, const InstDesc* insts, const RangeDes
 // Minimum waves per SIMD requested per chain size K: the largest value at which
 // the unrolled chain still compiles without spilling (measured on gfx950; the
 // hint only caps registers, so chains that fit more waves keep them).
-constexpr int f32_min_waves(int K) { return K <= 30 ? 4 : 3; }
+constexpr int f32_min_waves(int K) { return K <= 30 ? 4 : K <= 40 ? 3 : 2; }
 constexpr int f64_min_waves(int K) { return K <= 11 ? 4 : K <= 18 ? 3 : 2; }
 
 template <int K, bool BLOCK>
@@ -567,6 +567,19 @@ hipError_t qmc_switch(int K, int precision, const InstDesc* insts, const RangeDe
   return err;
 }
 
+// FP32 plain chains of 32..63 steps: unrolled like the shorter ones
+template <int... Ks>
+hipError_t qmc_switch_f32_long(int K, const InstDesc* insts, const RangeDesc* ranges, int n_ranges,
+                               int64_t n_items, const Aux64* aux64, const Aux32* aux32, const uint64_t* Z,
+                               double* sums, hipStream_t s, std::integer_sequence<int, Ks...>) {
+  hipError_t err = hipErrorInvalidValue;
+  ((K == Ks + kMaxUnrolledK + 1
+        ? (err = qmc_dispatch<Ks + kMaxUnrolledK + 1, false>(VECCHIA_FP32_LOOP, insts, ranges, n_ranges, n_items,
+                                                              aux64, aux32, Z, sums, s), 0)
+        : 0), ...);
+  return err;
+}
+
 }  // namespace
 
 hipError_t launch_qmc(int K, int precision, bool block, const InstDesc* d_insts, const RangeDesc* d_ranges,
@@ -574,6 +587,9 @@ hipError_t launch_qmc(int K, int precision, bool block, const InstDesc* d_insts,
                       const uint64_t* d_Z, double* sums, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
   if (K < 1 || K > kMaxM) return hipErrorInvalidValue;
+  if (K > kMaxUnrolledK && precision == VECCHIA_FP32_LOOP && !block)
+    return qmc_switch_f32_long(K, d_insts, d_ranges, n_ranges, n_items, aux64, aux32, d_Z, sums, s,
+                               std::make_integer_sequence<int, kMaxM - kMaxUnrolledK>{});
   if (K > kMaxUnrolledK)
     return qmc_gen_dispatch(precision, d_insts, d_ranges, n_ranges, n_items, aux64, aux32, d_Z, sums, s);
   if (block)

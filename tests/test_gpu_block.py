@@ -70,7 +70,7 @@ def test_fp32_block_logcdf_within_tolerance():
     torch = torch_cuda()
     from paper_2007_15195_amd import vecchia as V
     inst = W.uniform2500_matern15()
-    for m, p in ((5, 5), (10, 2)):
+    for m, p in ((5, 5), (10, 2), (15, 4)):     # (15, 4): terms of 64 variables, general kernel
         plan = V.vecchia_plan_block(inst.locs, inst.ordering, m, p, inst.cov)
         nt = V.plan_n_terms(plan)
         q32 = V.make_qmc(4096, 8, 3, V.VECCHIA_FP32_LOOP)
