@@ -6,14 +6,17 @@
 //   2. blocked right-looking Cholesky, block 32: chol_diag (one wave, LDS),
 //      chol_panel (one thread per row below the block), chol_update (16 x 16
 //      tiles of the trailing lower triangle);
-//   3. full_sov: one thread per lattice point, one workgroup per 256 points of
+//   3. chol_mirror copies L into the upper triangle (L^T), so that a column of L
+//      is contiguous;
+//   4. full_sov: one thread per lattice point, one workgroup per 256 points of
 //      one shift. Dimensions advance in blocks of 16: the block's partial sums
 //      b_a - sum_{c<j0} L_ac y_c come from the earlier y (read back from HBM,
-//      coalesced, each load feeding 16 FMAs) against L staged in LDS; inside the
-//      block the recursion runs in registers:
+//      coalesced, each load feeding 16 FMAs) against the column L[j0.., c] read
+//      through the scalar cache (uniform across the workgroup); inside the block
+//      the recursion runs in registers:
 //          e_a = Phi(t_a), log prod += log Phi(t_a), y_a = Phi^-1(max(w_a e_a, DBL_MIN)).
 //      Each workgroup leaves {max, sum exp(. - max)} of its points' log products;
-//   4. full_final: per shift l_r = log mean over points, then
+//   5. full_final: per shift l_r = log mean over points, then
 //      log F = log mean_r exp(l_r) and the delta-method SE over the shifts.
 // Lattice: Z_j from the first D - 1 primes; the shift of dimension j in
 // replicate r is SplitMix64 output 2^63 + r 2^32 + j of the call's seed.
@@ -33,7 +36,6 @@ namespace {
 constexpr int kCholB = 32;     // Cholesky block
 constexpr int kSovB = 16;      // SOV dimension block (registers)
 constexpr int kSovThreads = 256;
-constexpr int kSovChunk = 64;  // columns of L staged per LDS chunk
 
 __device__ double cov_value(double h, int family, double nu, double s2, double rho) {
 #pragma clang fp contract(off)
@@ -152,6 +154,23 @@ __global__ __launch_bounds__(256) void chol_update(double* __restrict__ A, int64
   A[i * D + j] -= s;
 }
 
+// Upper triangle := L^T (A[j][i] = A[i][j] for j < i), 32 x 32 tiles through LDS.
+__global__ __launch_bounds__(256) void chol_mirror(double* __restrict__ A, int64_t D) {
+  const int64_t ti = blockIdx.y, tj = blockIdx.x;
+  if (tj > ti) return;
+  __shared__ double T[32][33];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t i = ti * 32 + r, j = tj * 32 + tx;
+    T[r][tx] = (i < D && j < D && j < i) ? A[i * D + j] : 0.0;
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t j = tj * 32 + r, i = ti * 32 + tx;   // write A[j][i] = L[i][j]
+    if (i < D && j < D && j < i) A[j * D + i] = T[tx][r];
+  }
+}
+
 __device__ __forceinline__ double log_ncdf(double t) {
   return t < 0.0 ? log(0.5 * erfcx(-t * 0.70710678118654752440)) - 0.5 * t * t
                  : log1p(-0.5 * erfc(t * 0.70710678118654752440));
@@ -160,18 +179,19 @@ __device__ __forceinline__ double log_ncdf(double t) {
 __device__ __noinline__ double ncdf_full(double t) { return normcdf(t); }
 __device__ __noinline__ double ncdfinv_full(double u) { return normcdfinv(u); }
 
-struct SovArgs {
-  const double* L;     // D x D, lower triangle
-  const double* b;     // D
-  const uint64_t* Z;   // D - 1 generators
-  double* Y;           // (D - 1) x S, S = N R: y of every point, dimension-major
-  double2* part;       // R x gridDim.x partial {max, sum exp}
+// L: D x D with L in the lower triangle and L^T in the upper; b: D limits;
+// Z: D - 1 generators; Y: (D - 1) x S (S = N R), the y of every point,
+// dimension-major; part: R x gridDim.x partial {max, sum exp}. Separate
+// restrict-qualified arguments let the uniform column reads of L go through
+// the scalar cache.
+struct SovSizes {
   int64_t D, N, S;
   uint64_t seed;
 };
 
-__global__ __launch_bounds__(kSovThreads) void full_sov(SovArgs a) {
-  __shared__ double Lt[kSovChunk][kSovB];       // L[j0 + r][c0 + cc] at [cc][r]
+__global__ __launch_bounds__(kSovThreads) void full_sov(const double* __restrict__ L, const double* __restrict__ bl,
+                                                        const uint64_t* __restrict__ Zt, double* __restrict__ Y,
+                                                        double2* __restrict__ part, SovSizes a) {
   __shared__ double Ld[kSovB][kSovB + 1];       // the block's own rows
   __shared__ double red_m[kSovThreads / 64], red_s[kSovThreads / 64];
   const int r = blockIdx.y;
@@ -184,27 +204,24 @@ __global__ __launch_bounds__(kSovThreads) void full_sov(SovArgs a) {
     const int nb = (int)(D - j0 < kSovB ? D - j0 : kSovB);
     double acc[kSovB];
 #pragma unroll
-    for (int q = 0; q < kSovB; ++q) acc[q] = q < nb ? a.b[j0 + q] : 0.0;
-    // earlier dimensions: acc_q -= sum_{c < j0} L[j0 + q][c] y_c
-    for (int64_t c0 = 0; c0 < j0; c0 += kSovChunk) {
-      const int nc = (int)(j0 - c0 < kSovChunk ? j0 - c0 : kSovChunk);
-      __syncthreads();
-      for (int idx = threadIdx.x; idx < kSovChunk * kSovB; idx += kSovThreads) {
-        const int q = idx / kSovChunk, cc = idx - q * kSovChunk;
-        Lt[cc][q] = (q < nb && cc < nc) ? a.L[(j0 + q) * D + c0 + cc] : 0.0;
-      }
-      __syncthreads();
-      const double* Yc = a.Y + c0 * a.S + s;
-      for (int cc = 0; cc < nc; ++cc) {
-        const double yc = Yc[(int64_t)cc * a.S];
+    for (int q = 0; q < kSovB; ++q) acc[q] = q < nb ? bl[j0 + q] : 0.0;
+    // earlier dimensions: acc_q -= sum_{c < j0} L[j0 + q][c] y_c, the column
+    // L[j0.., c] being row c of the mirrored upper triangle (c < j0 <= j0 + q).
+    // All kSovB entries are read (one wide scalar load); in a last, ragged block
+    // the ones past the row end fall in row c + 1 or in the limits that follow A
+    // in the workspace, and only feed acc entries that are never used.
+    const double* __restrict__ Lu = L + j0;
+#pragma unroll 4
+    for (int64_t c = 0; c < j0; ++c) {
+      const double yc = Y[c * a.S + s];
+      const double* __restrict__ col = Lu + c * D;
 #pragma unroll
-        for (int q = 0; q < kSovB; ++q) acc[q] -= Lt[cc][q] * yc;
-      }
+      for (int q = 0; q < kSovB; ++q) acc[q] -= col[q] * yc;
     }
     __syncthreads();
     for (int idx = threadIdx.x; idx < kSovB * kSovB; idx += kSovThreads) {
       const int q = idx / kSovB, c = idx - q * kSovB;
-      Ld[q][c] = (q < nb && c <= q) ? a.L[(j0 + q) * D + j0 + c] : 0.0;
+      Ld[q][c] = (q < nb && c <= q) ? L[(j0 + q) * D + j0 + c] : 0.0;
     }
     __syncthreads();
     double yb[kSovB];
@@ -221,11 +238,11 @@ __global__ __launch_bounds__(kSovThreads) void full_sov(SovArgs a) {
         const int64_t dim = j0 + q;
         if (dim < D - 1) {
           const uint64_t S = splitmix64(a.seed, (1ULL << 63) | ((uint64_t)r << 32) | (uint64_t)dim);
-          const uint64_t U = (uint64_t)(p + 1) * a.Z[dim] + S;
+          const uint64_t U = (uint64_t)(p + 1) * Zt[dim] + S;
           const double w = lattice_coord_f64(U);
           const double y = ncdfinv_full(fmax(w * e, 2.2250738585072014e-308));
           yb[q] = y;
-          if (live) a.Y[dim * a.S + s] = y;
+          if (live) Y[dim * a.S + s] = y;
         }
       }
     }
@@ -247,7 +264,7 @@ __global__ __launch_bounds__(kSovThreads) void full_sov(SovArgs a) {
   if (threadIdx.x == 0) {
     double sum = 0.0;
     for (int k = 0; k < kSovThreads / 64; ++k) sum += red_s[k];
-    a.part[(int64_t)r * gridDim.x + blockIdx.x] = make_double2(M, sum);
+    part[(int64_t)r * gridDim.x + blockIdx.x] = make_double2(M, sum);
   }
 }
 
@@ -352,17 +369,22 @@ extern "C" vecchia_status vecchia_full_logcdf(vecchia_plan_t plan, const double*
     if (e == hipSuccess && rest > 0) {
       hipLaunchKernelGGL(chol_panel, dim3((unsigned)((rest + 255) / 256)), dim3(256), 0, s, A, D, k0, n);
       e = hipGetLastError();
-      const unsigned t = (unsigned)((rest + 15) / 16);
+      const unsigned t = (unsigned)((rest + 15) / 16);   // 16 x 16 tiles of the trailing triangle
       if (e == hipSuccess) {
         hipLaunchKernelGGL(chol_update, dim3(t, t), dim3(256), 0, s, A, D, k0, n);
         e = hipGetLastError();
       }
     }
   }
+  if (e == hipSuccess) {
+    const unsigned t32 = (unsigned)((D + 31) / 32);
+    hipLaunchKernelGGL(chol_mirror, dim3(t32, t32), dim3(256), 0, s, A, D);
+    e = hipGetLastError();
+  }
   const unsigned nblk = (unsigned)((N + kSovThreads - 1) / kSovThreads);
   if (e == hipSuccess) {
-    SovArgs sa{A, b, Zt, Y, part, D, N, S, q->seed};
-    hipLaunchKernelGGL(full_sov, dim3(nblk, (unsigned)R), dim3(kSovThreads), 0, s, sa);
+    SovSizes sz{D, N, S, q->seed};
+    hipLaunchKernelGGL(full_sov, dim3(nblk, (unsigned)R), dim3(kSovThreads), 0, s, A, b, Zt, Y, part, sz);
     e = hipGetLastError();
   }
   if (e == hipSuccess) {
