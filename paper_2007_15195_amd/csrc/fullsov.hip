@@ -26,6 +26,7 @@
 #include <cmath>
 #include <string>
 
+#include "device_cov.h"
 #include "lattice.h"
 #include "runtime.h"
 #include "vecchia.h"
@@ -36,17 +37,6 @@ namespace {
 constexpr int kCholB = 32;     // Cholesky block
 constexpr int kSovB = 16;      // SOV dimension block (registers)
 constexpr int kSovThreads = 256;
-
-__device__ double cov_value(double h, int family, double nu, double s2, double rho) {
-#pragma clang fp contract(off)
-  if (family == VECCHIA_COV_EXPONENTIAL || nu == 0.5) return s2 * exp(-h / rho);
-  if (nu == 1.5) {
-    const double a = 1.7320508075688772 * h / rho;
-    return s2 * (1.0 + a) * exp(-a);
-  }
-  const double a = 2.23606797749979 * h / rho;
-  return s2 * (1.0 + a + a * a / 3.0) * exp(-a);
-}
 
 struct CovArgs {
   const double* xs;
@@ -70,7 +60,7 @@ __global__ __launch_bounds__(256) void full_cov_build(CovArgs a, int64_t D, doub
 #pragma clang fp contract(off)
     const double dx = a.xs[i] - a.xs[j];
     const double dy = a.ys[i] - a.ys[j];
-    v = cov_value(sqrt(dx * dx + dy * dy), a.family, a.nu, a.sigma2, a.range);
+    v = cov_kernel(sqrt(dx * dx + dy * dy), a.family, a.nu, a.sigma2, a.range);
     if (i == j) v += a.nugget;
   }
   A[i * D + j] = v;

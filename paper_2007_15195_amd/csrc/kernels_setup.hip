@@ -26,22 +26,12 @@
 //
 // A pivot <= 0 (or NaN) marks the term NOT_PD: its outputs become NaN and the
 // instance's bad_term is lowered to i.
+#include "device_cov.h"
 #include "fp32_math_coeffs.h"
 #include "vecchia_internal.h"
 
 namespace vecchia {
 namespace {
-
-__device__ double cov_kernel(double h, int family, double nu, double s2, double rho) {
-#pragma clang fp contract(off)
-  if (family == VECCHIA_COV_EXPONENTIAL || nu == 0.5) return s2 * exp(-h / rho);
-  if (nu == 1.5) {
-    const double a = 1.7320508075688772 * h / rho;   // sqrt(3) h / rho
-    return s2 * (1.0 + a) * exp(-a);
-  }
-  const double a = 2.23606797749979 * h / rho;       // sqrt(5) h / rho
-  return s2 * (1.0 + a + a * a / 3.0) * exp(-a);
-}
 
 __device__ __forceinline__ int find_inst(const int64_t* __restrict__ bases, int n, int64_t t) {
   int lo = 0, hi = n - 1;
