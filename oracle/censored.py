@@ -27,6 +27,10 @@ and every factor conditions on N_i, the m nearest preceding sites, instead:
 With m = D - 1 every N_i is every preceding site and the product is L_1
 exactly. At scale r the limits are b = x / r and each density factor gains the
 Jacobian 1 / r.
+
+Infinite values (reading, as in sov): a factor any of whose variables is an
+uncensored site with an infinite value, or has the limit -inf, is 0 (the
+density vanishes at infinity; a probability of X <= -inf is 0).
 """
 from __future__ import annotations
 
@@ -76,6 +80,9 @@ def _terms(get_C, b_all, nbrs, n_obs, n_points, n_shifts, seed, scale, idx, proc
         C = get_C(v)
         b = b_all[v]
         eq = v < n_obs
+        if np.any(b == -np.inf) or np.any(np.isinf(b[eq])):
+            out[int(i)] = (-math.inf, 0.0)
+            continue
         if i < n_obs:
             # density factor: every neighbour precedes i, so every one is observed
             _, mu, S = conditional(C, b, np.append(eq[:-1], False))

@@ -17,6 +17,12 @@ one from the R shift replicates:
     se^2 = sum_r (n_r / n - d_r / d)^2 / (R (R - 1)).
 When a factor e_a is exactly 0 the sample's products are 0 and its later
 coordinates are not used; u = w e is clamped below at the smallest normal double.
+
+Infinite limits (the paper is silent; reading): b_a = +inf leaves variable a
+unconstrained (e_a = 1, so it only shapes the later conditional means), and a
+term any of whose limits is -inf is 0 (log-term -inf, SE 0). Its numerator
+vanishes; when the -inf limit is a conditioning one the ratio is 0 / 0, and
+taking it as 0 keeps the product of eq. (6) equal to Phi_D = 0.
 """
 from __future__ import annotations
 
@@ -81,6 +87,13 @@ def term_sums(C: np.ndarray, b: np.ndarray, n_points: int, n_shifts: int, seed: 
 def term_estimate(C: np.ndarray, b: np.ndarray, n_points: int, n_shifts: int, seed: int,
                   term: int, Z: list | None = None, split: int | None = None):
     """Return (log_term, se) of one Vecchia term (split: as term_sums)."""
+    if np.any(np.asarray(b) == -np.inf):
+        # a covariance that is not positive definite is reported first
+        try:
+            np.linalg.cholesky(C)
+        except np.linalg.LinAlgError as exc:
+            raise NotPositiveDefinite(str(exc)) from exc
+        return -math.inf, 0.0
     if len(b) == 1:
         if not C[0, 0] > 0.0:
             raise NotPositiveDefinite("variance <= 0")

@@ -28,6 +28,9 @@ MUTATIONS = {
     "missing_diagonal_scaling": ("ndtr(acc / L[a, a])", "ndtr(acc)"),
     "first_factor_unscaled": ("e1 = ndtr(b[0] / L[0, 0])", "e1 = ndtr(b[0])"),
     "inverse_of_w_without_e": ("u = np.maximum(w * e, DBL_MIN)", "u = np.maximum(w, DBL_MIN)"),
+    "minus_inf_rule_dropped": ("if np.any(np.asarray(b) == -np.inf):", "if False:"),
+    "plus_inf_taken_as_minus_inf": ("if np.any(np.asarray(b) == -np.inf):",
+                                    "if np.any(np.isinf(np.asarray(b))):"),
 }
 
 
@@ -70,6 +73,18 @@ def _pins_pass(sov_mod) -> bool:
         b1, b2 = b[0] / math.sqrt(2.0), b[1] / math.sqrt(1.5)
         want = math.log(cf.bivariate_cdf(b1, b2, corr) / ndtr(b1))
         if not abs(r["terms"][1, 0] - want) <= 4 * r["terms"][1, 1] + 1e-9:
+            return False
+        # infinite limits: +inf leaves a component unconstrained (here the exact
+        # m = D - 1 product then is the bivariate CDF of the other two), and a
+        # -inf limit gives log F = -inf
+        C = covariance.cov_matrix(pts, covariance.COV_EXPONENTIAL, 0.5, 1.0, 0.4, 0.0)
+        with np.errstate(all="ignore"):
+            r = oracle.logcdf_from_cov(C, np.array([0.4, np.inf, -0.3]), [[], [0], [0, 1]], 2048, 8, 5)
+            want = math.log(cf.bivariate_owen(0.4, -0.3, C[0, 2]))
+            if not abs(r["logF"] - want) <= 4 * r["se"] + 1e-9:
+                return False
+            r = oracle.logcdf_from_cov(C, np.array([0.4, -np.inf, -0.3]), [[], [0], [0, 1]], 256, 4, 5)
+        if r["logF"] != -math.inf:
             return False
         return True
     finally:
