@@ -119,7 +119,8 @@ def logcdf_mixture(eval_logF, beta: float, gamma: float, n_nodes: int, eval_sear
     se = np.array([p[1] for p in node])
     summand = logw + logF
     logG = logsumexp(summand)
-    frac = np.exp(summand - logG)
+    # G = 0 (every node 0, e.g. a -inf threshold) is exact: SE 0
+    frac = np.exp(summand - logG) if logG > -math.inf else np.zeros_like(summand)
     se_G = math.sqrt(math.fsum((frac * se) ** 2))
     return dict(logG=logG, se=se_G, window=(lo, hi), v=v, scales=scales, node_logF=logF,
                 search_logF=np.array(search))
