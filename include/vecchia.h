@@ -159,6 +159,8 @@ vecchia_status vecchia_plan_from_cov(const double* cov_host, int64_t D, const in
  * observed neighbours (dimension: its censored neighbours + 1); the per-term
  * output holds the density terms with SE 0. vecchia_mixture_logcdf on it
  * returns log G_I(x). With no observed site the plan equals vecchia_plan's.
+ * An observed site whose value is infinite has density 0: every term that
+ * holds it is -inf (SE 0).
  * Errors: as vecchia_plan, and INVALID for flags other than 0 / 1. */
 vecchia_status vecchia_plan_censored(const double* locs_host, int64_t D, int32_t dim, int32_t ordering,
                                      const int64_t* perm_in_host, const uint8_t* observed_host, int32_t m,
@@ -229,6 +231,9 @@ vecchia_status vecchia_plan_neighbours(vecchia_plan_t plan, int64_t* perm_host, 
  * covariance with the plan's family and nu. q: QMC size, seed and precision.
  * out_dev: 2 doubles, {log F, standard error}. terms_dev: NULL or D x 2
  * doubles {log term, standard error} in user index order.
+ * Infinite thresholds: +inf leaves a component unconstrained; a -inf threshold
+ * gives log F = -inf, every term whose variables include it being exactly -inf
+ * with SE 0 (other terms are unchanged). NaN thresholds give NaN.
  * Enqueues term_setup, the QMC kernels and finalize_logsum on hip_stream.
  * Errors: INVALID (bad arguments; nothing enqueued), NOMEM, HIP. */
 vecchia_status vecchia_logcdf(vecchia_plan_t plan, const double* x_dev, double scale,
@@ -288,7 +293,8 @@ vecchia_status vecchia_profile_reset(void);
  *   2. the window [lo, hi] of vecchia_mixture_rule and n_nodes-point
  *      Gauss-Legendre on it at q's full size, combined on the device:
  *   out_dev[0] = log G = log sum_k w_k e^(-v_k) h(r(v_k)),
- *   out_dev[1] = its standard error (first-order propagation of the node SEs).
+ *   out_dev[1] = its standard error (first-order propagation of the node SEs;
+ *                0 when G = 0, i.e. every node is 0).
  * Every node uses q->seed (common random numbers). x_dev: D thresholds, user
  * order (device). cov_override as in vecchia_logcdf. nodes_dev (may be NULL):
  * n_nodes x {log h, se} per node (device). Synchronises hip_stream once

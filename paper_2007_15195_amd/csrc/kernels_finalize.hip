@@ -2,8 +2,8 @@
 //
 // term_finalize: one wave per term (all instances of a launch). A term with no
 // SOV dimension (k = 0; in a censored plan also a density term or a censored
-// term whose neighbours are all uncensored) takes the exact value term_setup
-// wrote, with SE 0; otherwise the wave's lanes take the
+// term whose neighbours are all uncensored), or one that term_setup found to be
+// 0 (a -inf limit), takes the exact value term_setup wrote, with SE 0; otherwise the wave's lanes take the
 // shifts (lane r sums shift r's chunks in order), fixed butterflies give the
 // totals, and
 //     log-term = log(sum_r num_r) - log(sum_r den_r)
@@ -49,7 +49,7 @@ __global__ __launch_bounds__(64 * kFinalizeWaves) void term_finalize(
   const int64_t i = t - term_bases[ii];
   const int R = I.n_shifts;
   double lt, se2;
-  if (I.sovk[i] == 0) {
+  if (I.sovk[i] == 0 || aux64[t].e0 < 0.0) {   // exact, or a term that is 0 (e0 = -1)
     lt = aux64[t].lt0;
     se2 = 0.0;
   } else {
@@ -146,7 +146,7 @@ __device__ void combine_wave(const double* __restrict__ node_out, double logw, i
     const double sum = wave_sum(on ? exp(c - mx) : 0.0);
     logG = mx + log(sum);
   }
-  const double frac = on ? exp(c - logG) : 0.0;
+  const double frac = (on && logG > -HUGE_VAL) ? exp(c - logG) : 0.0;   // G = 0 is exact: SE 0
   const double var = wave_sum(on ? (frac * se) * (frac * se) : 0.0);
   if (lane == 0) {
     out[0] = logG;

@@ -135,6 +135,9 @@ __device__ __forceinline__ void item_f64(const Item& it, const Aux64* __restrict
       if (BLOCK || a < K) prod *= e;
     }
     if (live) {
+      // no contraction here: a fused prod * e_{K-1} + acc_den would add the
+      // unrounded product to den while num takes the rounded one
+#pragma clang fp contract(off)
       if (BLOCK) {
         acc_den += head;
         acc_num += prod;
@@ -460,6 +463,7 @@ __device__ __forceinline__ void item_f64_gen(const Item& it, const Aux64* __rest
       if (block || a < K) prod *= e;
     }
     if (live) {
+#pragma clang fp contract(off)
       if (block) {
         acc_den += head;
         acc_num += prod;

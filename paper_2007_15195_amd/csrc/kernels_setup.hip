@@ -26,6 +26,13 @@
 //
 // A pivot <= 0 (or NaN) marks the term NOT_PD: its outputs become NaN and the
 // instance's bad_term is lowered to i.
+//
+// Infinite thresholds: +inf leaves a variable unconstrained (its factor is 1;
+// the FP32 rows cap the scaled limit at 2^20, where Phi is 1 in FP32 as well).
+// A term with a limit of -inf, or with an observed site whose value is
+// infinite (zero density), is 0: e0 = -1 marks it, lt0 = -inf is its value
+// with SE 0, and its rows get finite limits so the QMC kernels run a harmless
+// chain whose sums are never read.
 #include "device_cov.h"
 #include "fp32_math_coeffs.h"
 #include "vecchia_internal.h"
@@ -68,14 +75,17 @@ __global__ __launch_bounds__(64) void term_setup(const InstDesc* __restrict__ in
   const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   const int q = __popcll(eq_mask);
   const int slot = lane >= k ? lane : eq ? __popcll(eq_mask & below) : q + (lane - __popcll(eq_mask & below));
+  double bl = 0.0;
   if (lane < n) {
     pv[slot] = (int)v;
     if (!I.covmat) {
       px[slot] = I.xs[v];
       py[slot] = I.ys[v];
     }
-    pb[slot] = I.x[I.perm[v]] * I.inv_scale;
+    bl = I.x[I.perm[v]] * I.inv_scale;
+    pb[slot] = bl;
   }
+  const bool zero = __ballot(lane < n && (bl == -HUGE_VAL || (v < I.n_obs && __builtin_isinf(bl)))) != 0;
   __syncthreads();
   for (int idx = lane; idx < n * n; idx += 64) {
     const int a = idx / n;
@@ -138,11 +148,13 @@ __global__ __launch_bounds__(64) void term_setup(const InstDesc* __restrict__ in
       const double sc = kPhiScale / laa;
       float* row = reinterpret_cast<float*>(I.prep) + off;
       for (int c = 0; c < a; ++c) row[c] = (float)(C[lane][q + c] * sc);
-      row[a] = bad ? __builtin_nanf("") : (float)(bs * sc);
+      double bv = bs * sc;
+      if (bv > 0x1p20) bv = 0x1p20;
+      row[a] = bad ? __builtin_nanf("") : zero ? 0.0f : (float)bv;
     } else {
       double* row = reinterpret_cast<double*>(I.prep) + off;
       for (int c = 0; c < a; ++c) row[c] = C[lane][q + c] / laa;
-      row[a] = bad ? nan : bs / laa;
+      row[a] = bad ? nan : zero ? 0.0 : bs / laa;
     }
   }
   if (lane == 0) {
@@ -175,6 +187,11 @@ __global__ __launch_bounds__(64) void term_setup(const InstDesc* __restrict__ in
         a.ec0 = bad ? __builtin_nanf("") : (float)normcdf(-b0);
         aux32[t] = a;
       }
+    }
+    if (zero && !bad) {
+      aux64[t].e0 = -1.0;
+      aux64[t].lt0 = -HUGE_VAL;
+      if (f32) aux32[t] = Aux32{0.5f, 0.0f, 0.5f, 1.0f};
     }
     if (bad) atomicMin((long long*)I.bad_term, (long long)i);
   }

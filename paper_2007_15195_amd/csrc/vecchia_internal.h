@@ -67,7 +67,9 @@ struct RangeDesc {
 };
 
 // Auxiliary per-term values written by term_setup.
-struct Aux64 { double e0; double lt0; };   // Phi(b_0/L_00) and its log
+// Phi(b_0/L_00) and its log; e0 = -1 marks a term that is 0 (a -inf limit),
+// whose value lt0 = -inf is exact.
+struct Aux64 { double e0; double lt0; };
 // FP32 form of e0 = Phi(b_0/L_00): e0 = em0 * 2^en0 (en0 = 0 unless b_0/L_00 <= 0),
 // ec0 = 1 - e0, neg0 = 1 if b_0/L_00 <= 0.
 struct Aux32 { float em0, en0, ec0, neg0; };
