@@ -175,3 +175,51 @@ def test_profile_hook_counts_the_main_launch():
     assert launches == 3 and ms > 0
     assert steps == 3 * (600 - 10) * 4 * 2048 * 10
     V.vecchia_plan_destroy(plan)
+
+
+def test_server_mix_of_plan_kinds_equals_standalone_calls():
+    # plans of every kind in one stream of overlapping requests: a long chain
+    # (general kernel), joint block terms, a censored replicate and an explicit
+    # covariance; each result equals the same request run alone, bit for bit
+    torch = torch_cuda()
+    from paper_2007_15195_amd import vecchia as V
+    long_i = W.small_random_instance(150, 45, 61, n_points=300, n_shifts=3, precision=W.PREC_FP32)
+    blk_i = W.small_random_instance(240, 4, 62, n_points=500, n_shifts=3, precision=W.PREC_FP32)
+    rep = W.censored_replicate(300, 10, 63, frac_obs=0.1, n_points=400, n_shifts=3)
+    S = 0.6 * np.eye(12) + 0.4
+    cov_x = np.random.default_rng(64).normal(0.5, 0.5, size=12)
+    reqs = [
+        (V.vecchia_plan(long_i.locs, long_i.ordering, long_i.m, long_i.cov), long_i.x,
+         V.make_qmc(300, 3, 5, V.VECCHIA_FP32_LOOP), 1.0),
+        (V.vecchia_plan_block(blk_i.locs, blk_i.ordering, 4, 3, blk_i.cov), blk_i.x,
+         V.make_qmc(500, 3, 6, V.VECCHIA_FP64), 1.3),
+        (V.vecchia_plan_censored(rep.inst.locs, rep.observed, rep.inst.ordering, rep.inst.m, rep.inst.cov),
+         rep.inst.x, V.make_qmc(400, 3, 7, V.VECCHIA_FP32_LOOP), 1.1),
+        (V.vecchia_plan_from_cov(S, 11), cov_x, V.make_qmc(256, 4, 8, V.VECCHIA_FP64), 1.0),
+    ]
+    xs = [torch.tensor(x, dtype=torch.float64, device="cuda") for _, x, _, _ in reqs]
+    alone = []
+    for (p, _, q, sc), x in zip(reqs, xs):
+        out = torch.empty(2, dtype=torch.float64, device="cuda")
+        V.vecchia_logcdf(p, x, q, out, scale=sc)
+        torch.cuda.synchronize()
+        alone.append(out.cpu().numpy())
+    assert all(np.isfinite(a[0]) for a in alone)
+    srv = V.vecchia_server_create(1 << 30, 3)
+    tickets = [(j, V.vecchia_submit(srv, p, xs[j], q, scale=sc))
+               for _ in range(2) for j, (p, _, q, sc) in enumerate(reqs)]
+    results = {}
+    t_end = time.time() + 60
+    while len(results) < len(tickets) and time.time() < t_end:
+        for k, (j, t) in enumerate(tickets):
+            if k not in results:
+                r = V.vecchia_poll(srv, t)
+                if r is not None:
+                    results[k] = (j, r)
+        time.sleep(0.001)
+    assert len(results) == len(tickets)
+    for k, (j, (lf, se, _)) in results.items():
+        assert lf == alone[j][0] and se == alone[j][1], (k, j, lf, alone[j])
+    V.vecchia_server_destroy(srv)
+    for p, _, _, _ in reqs:
+        V.vecchia_plan_destroy(p)
