@@ -60,14 +60,15 @@ def block_plan(locs, rule: int, m: int, p: int, perm=None):
 
 
 def _job(args):
-    g, C, b, split, n_points, n_shifts, seed = args
-    return sov.term_estimate(C, b, n_points, n_shifts, seed, g, split=split)
+    g, C, b, split, n_points, n_shifts, seed, independent = args
+    return sov.term_estimate(C, b, n_points, n_shifts, seed, g, split=split, independent=independent)
 
 
 def logcdf_block(locs, x, m, p, family, nu, sigma2, rho, nugget, rule, n_points, n_shifts, seed,
-                 scale: float = 1.0, perm=None, processes: int = 1, plan_cache=None):
+                 scale: float = 1.0, perm=None, processes: int = 1, plan_cache=None,
+                 independent: bool = False):
     """Block Vecchia log-CDF. Returns dict(logF, se, terms (one row per group,
-    group order), perm, groups, conds)."""
+    group order), perm, groups, conds). independent: as sov.term_estimate."""
     locs = np.asarray(locs, dtype=np.float64)
     x = np.asarray(x, dtype=np.float64)
     if plan_cache is not None:
@@ -80,7 +81,7 @@ def logcdf_block(locs, x, m, p, family, nu, sigma2, rho, nugget, rule, n_points,
     for g, (G, Cg) in enumerate(zip(groups, conds)):
         v = np.concatenate([Cg, G])
         C = covariance.cov_matrix(s[v], family, nu, sigma2, rho, nugget)
-        jobs.append((g, C, b_all[v], len(Cg), n_points, n_shifts, seed))
+        jobs.append((g, C, b_all[v], len(Cg), n_points, n_shifts, seed, independent))
     from concurrent.futures import ProcessPoolExecutor
     if processes <= 1 or len(jobs) < 2:
         res = [_job(j) for j in jobs]

@@ -71,7 +71,7 @@ def conditional(C: np.ndarray, b: np.ndarray, eq: np.ndarray):
     return A, mu, 0.5 * (S + S.T)
 
 
-def _terms(get_C, b_all, nbrs, n_obs, n_points, n_shifts, seed, scale, idx, processes):
+def _terms(get_C, b_all, nbrs, n_obs, n_points, n_shifts, seed, scale, idx, processes, independent=False):
     """Evaluate the terms idx; returns {plan index: (log term, se)}."""
     out = {}
     jobs = []
@@ -93,7 +93,7 @@ def _terms(get_C, b_all, nbrs, n_obs, n_points, n_shifts, seed, scale, idx, proc
             out[int(i)] = (-0.5 * (LOG_2PI + math.log(var)) - 0.5 * z * z - math.log(scale), 0.0)
         else:
             A, mu, S = conditional(C, b, eq)
-            jobs.append((int(i), S, b[A] - mu, n_points, n_shifts, seed))
+            jobs.append((int(i), S, b[A] - mu, n_points, n_shifts, seed, independent))
     for (i, *_), r in zip(jobs, _run_terms(jobs, processes)):
         out[i] = r
     return out
@@ -110,7 +110,7 @@ def _assemble(res, perm, D):
 
 def loglik(locs, x, observed, m, family, nu, sigma2, rho, nugget, rule, n_points, n_shifts,
            seed, scale: float = 1.0, perm=None, terms_subset=None, processes: int = 1,
-           plan_cache=None):
+           plan_cache=None, independent: bool = False):
     """Vecchia log L_r(x) of one replicate (r = scale). observed: D flags in
     user order (True = uncensored). Returns dict(logL, se, terms (D x 2, user
     order), perm, nbrs, n_obs); terms_subset restricts the terms (plan indices)."""
@@ -125,7 +125,7 @@ def loglik(locs, x, observed, m, family, nu, sigma2, rho, nugget, rule, n_points
     b_all = x[perm2] / scale
     get_C = lambda v: covariance.cov_matrix(s[v], family, nu, sigma2, rho, nugget)
     idx = range(D) if terms_subset is None else terms_subset
-    res = _terms(get_C, b_all, nbrs, n_obs, n_points, n_shifts, seed, scale, idx, processes)
+    res = _terms(get_C, b_all, nbrs, n_obs, n_points, n_shifts, seed, scale, idx, processes, independent)
     logL, se, terms = _assemble(res, perm2, D)
     return dict(logL=logL, se=se, terms=terms, perm=perm2, nbrs=nbrs, n_obs=n_obs)
 

@@ -62,12 +62,17 @@ def splitmix64_output(seed: int, n: int) -> int:
     return splitmix64_mix((seed + (n + 1) * GOLDEN_GAMMA) & MASK64)
 
 
-def shift(seed: int, term: int, r: int, dim: int) -> int:
-    """Random shift of dimension `dim` in replicate `r` of plan-order term `term`."""
+def shift(seed: int, term: int, r: int, dim: int, second: bool = False) -> int:
+    """Random shift of dimension `dim` in replicate `r` of plan-order term `term`.
+    second: the term's second, independent lattice (the denominator's points of
+    the independent-points estimator), output number key + 2^61; no first-lattice
+    key (below 2^53, or 2^62 + less than 2^54) and no full-dimension key
+    (from 2^63) has bit 61 set."""
     assert 0 <= r < MAX_SHIFTS and 0 <= dim < 64 and term >= 0
+    salt = (1 << 61) if second else 0
     if dim < 32:
-        return splitmix64_output(seed, (term << 21) | (r << 5) | dim)
-    return splitmix64_output(seed, (1 << 62) | (term << 22) | (r << 6) | dim)
+        return splitmix64_output(seed, salt | (term << 21) | (r << 5) | dim)
+    return splitmix64_output(seed, salt | (1 << 62) | (term << 22) | (r << 6) | dim)
 
 
 def full_shift(seed: int, r: int, dim: int) -> int:

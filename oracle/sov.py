@@ -42,13 +42,14 @@ class NotPositiveDefinite(Exception):
 
 
 def term_sums(C: np.ndarray, b: np.ndarray, n_points: int, n_shifts: int, seed: int,
-              term: int, Z: list | None = None, split: int | None = None):
+              term: int, Z: list | None = None, split: int | None = None, second: bool = False):
     """Return (L, num[R], den[R]): per-shift lattice means of the numerator and
     denominator integrands of the term with covariance C and limits b.
 
     split (default n - 1): the denominator is the CDF of the first `split`
     variables, E[prod_{a<split} e_a] (a joint block term of Section 3.2 has its
-    conditioning variables first and its group last); split = 0 gives 1."""
+    conditioning variables first and its group last); split = 0 gives 1.
+    second: use the term's second lattice (lattice.shift(..., second=True))."""
     n = len(b)
     try:
         L = np.linalg.cholesky(C)
@@ -66,7 +67,7 @@ def term_sums(C: np.ndarray, b: np.ndarray, n_points: int, n_shifts: int, seed: 
         head = np.ones(n_points) if split == 0 else (prod.copy() if split == 1 else None)
         ys = np.zeros((k, n_points))
         for a in range(1, n):              # 0-based variable a = 1..k
-            w = lattice.points(n_points, a - 1, lattice.shift(seed, term, r, a - 1), Z)
+            w = lattice.points(n_points, a - 1, lattice.shift(seed, term, r, a - 1, second), Z)
             alive = e > 0.0
             u = np.maximum(w * e, DBL_MIN)
             y = np.where(alive, ndtri(u), 0.0)
@@ -85,8 +86,15 @@ def term_sums(C: np.ndarray, b: np.ndarray, n_points: int, n_shifts: int, seed: 
 
 
 def term_estimate(C: np.ndarray, b: np.ndarray, n_points: int, n_shifts: int, seed: int,
-                  term: int, Z: list | None = None, split: int | None = None):
-    """Return (log_term, se) of one Vecchia term (split: as term_sums)."""
+                  term: int, Z: list | None = None, split: int | None = None,
+                  independent: bool = False):
+    """Return (log_term, se) of one Vecchia term (split: as term_sums).
+
+    independent: the paper-literal form that estimates the numerator and the
+    denominator from separate point sets: the numerator from the term's lattice,
+    the denominator from its second lattice; the two estimates are independent,
+    so their relative variances add:
+        se^2 = [sum_r (n_r / n - 1)^2 + sum_r (d_r / d - 1)^2] / (R (R - 1))."""
     if np.any(np.asarray(b) == -np.inf):
         # a covariance that is not positive definite is reported first
         try:
@@ -100,6 +108,8 @@ def term_estimate(C: np.ndarray, b: np.ndarray, n_points: int, n_shifts: int, se
         with np.errstate(divide="ignore"):
             return float(np.log(ndtr(b[0] / math.sqrt(C[0, 0])))), 0.0
     _, num, den = term_sums(C, b, n_points, n_shifts, seed, term, Z, split)
+    if independent:
+        _, _, den = term_sums(C, b, n_points, n_shifts, seed, term, Z, split, second=True)
     nh = np.mean(num)
     dh = np.mean(den)
     with np.errstate(divide="ignore", invalid="ignore"):
@@ -107,5 +117,8 @@ def term_estimate(C: np.ndarray, b: np.ndarray, n_points: int, n_shifts: int, se
     R = n_shifts
     if R < 2:
         return log_term, float("nan")
-    se2 = np.sum((num / nh - den / dh) ** 2) / (R * (R - 1))
+    if independent:
+        se2 = (np.sum((num / nh - 1.0) ** 2) + np.sum((den / dh - 1.0) ** 2)) / (R * (R - 1))
+    else:
+        se2 = np.sum((num / nh - den / dh) ** 2) / (R * (R - 1))
     return log_term, float(math.sqrt(se2))

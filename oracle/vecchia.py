@@ -30,8 +30,9 @@ def plan(locs: np.ndarray, rule: int, m: int, perm: np.ndarray | None = None):
 
 
 def _term_job(args):
-    (i, C, b, n_points, n_shifts, seed) = args
-    return sov.term_estimate(C, b, n_points, n_shifts, seed, i)
+    (i, C, b, n_points, n_shifts, seed, *rest) = args
+    independent = bool(rest[0]) if rest else False
+    return sov.term_estimate(C, b, n_points, n_shifts, seed, i, independent=independent)
 
 
 def _run_terms(jobs, processes: int):
@@ -43,12 +44,13 @@ def _run_terms(jobs, processes: int):
 
 def logcdf(locs, x, m, family, nu, sigma2, rho, nugget, rule, n_points, n_shifts, seed,
            scale: float = 1.0, perm=None, terms_subset=None, processes: int = 1,
-           plan_cache=None):
+           plan_cache=None, independent: bool = False):
     """Vecchia log-CDF of a zero-mean GP at thresholds x / scale.
 
     Returns dict(logF, se, terms (D x 2, user order; NaN outside terms_subset),
     perm, nbrs). terms_subset: plan indices to evaluate (default all); logF and
-    se then cover only those terms.
+    se then cover only those terms. independent: separate point sets for each
+    term's numerator and denominator (sov.term_estimate).
     """
     locs = np.asarray(locs, dtype=np.float64)
     x = np.asarray(x, dtype=np.float64)
@@ -64,7 +66,7 @@ def logcdf(locs, x, m, family, nu, sigma2, rho, nugget, rule, n_points, n_shifts
     for i in idx:
         v = np.concatenate([nbrs[i], [i]]).astype(np.int64)
         C = covariance.cov_matrix(s[v], family, nu, sigma2, rho, nugget)
-        jobs.append((int(i), C, b_all[v], n_points, n_shifts, seed))
+        jobs.append((int(i), C, b_all[v], n_points, n_shifts, seed, independent))
     res = _run_terms(jobs, processes)
     terms = np.full((D, 2), np.nan)
     for (i, *_), (lt, se) in zip(jobs, res):
@@ -76,7 +78,7 @@ def logcdf(locs, x, m, family, nu, sigma2, rho, nugget, rule, n_points, n_shifts
 
 
 def logcdf_from_cov(Sigma, x, nbrs, n_points, n_shifts, seed, scale: float = 1.0,
-                    processes: int = 1):
+                    processes: int = 1, independent: bool = False):
     """Vecchia log-CDF for an explicit covariance, identity ordering and given
     neighbour lists (nbrs[i] must hold indices < i, in the order to use)."""
     Sigma = np.asarray(Sigma, dtype=np.float64)
@@ -85,7 +87,7 @@ def logcdf_from_cov(Sigma, x, nbrs, n_points, n_shifts, seed, scale: float = 1.0
     jobs = []
     for i in range(D):
         v = np.concatenate([np.asarray(nbrs[i], dtype=np.int64), [i]])
-        jobs.append((i, Sigma[np.ix_(v, v)], b_all[v], n_points, n_shifts, seed))
+        jobs.append((i, Sigma[np.ix_(v, v)], b_all[v], n_points, n_shifts, seed, independent))
     res = _run_terms(jobs, processes)
     terms = np.array(res, dtype=np.float64).reshape(D, 2)
     return dict(logF=math.fsum(terms[:, 0]), se=math.sqrt(math.fsum(terms[:, 1] ** 2)),
