@@ -14,7 +14,8 @@ ordering + the GPU nearest-preceding-neighbour kernel) followed by
 vecchia_logcdf (covariance + Cholesky, the QMC kernels, the segmented log-sum).
 K steps are timed between two device synchronisations; value = terms per second
 (D terms per step). The line also carries samples/s, the log-CDF-only rate,
-the plain FP64 rate on the same inputs, the FP32-vs-FP64 error, the roofline of
+the plain FP64 rate on the same inputs, the independent-points estimator's
+time and SE beside the shared lattice's, the FP32-vs-FP64 error, the roofline of
 the dominant kernel (its HIP-event time over the timed region), the CPU oracle
 baseline on a bounded sample, and one object per further workload:
   c1_grid     D = 400 on a 20 x 20 grid, exponential covariance, coordinate
@@ -531,6 +532,19 @@ def main():
     torch.cuda.synchronize()
     ms_fp64 = 1e3 * (time.perf_counter() - t0) / args.fp64_steps
     t32, t64 = terms32.cpu().numpy(), terms64.cpu().numpy()
+
+    # ---- the paper-literal estimator (separate points for each term's numerator
+    # and denominator) against the shared lattice, same N x R: time and SE
+    qind = V.make_qmc(inst.qmc.n_points, inst.qmc.n_shifts, inst.qmc.seed, V.VECCHIA_FP32_LOOP, independent=True)
+    V.vecchia_logcdf(plan, x, qind, out, stream=sp)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n_ind = max(1, args.steps // 2)
+    for _ in range(n_ind):
+        V.vecchia_logcdf(plan, x, qind, out, stream=sp)
+    torch.cuda.synchronize()
+    ms_ind = 1e3 * (time.perf_counter() - t0) / n_ind
+    lind = out.cpu().numpy().copy()
     V.vecchia_plan_destroy(plan)
 
     # measured issue rates (wave64 instructions per CU per ns) and the ceiling
@@ -565,6 +579,9 @@ def main():
                         "samples_per_s": samples_per_step / (ms_logcdf * 1e-3)},
         "fp64_plain": {"ms": ms_fp64, "terms_per_s": D / (ms_fp64 * 1e-3),
                        "fp32_speedup": ms_fp64 / ms_logcdf},
+        "independent_points": {"ms": ms_ind, "logF": float(lind[0]), "se": float(lind[1]),
+                               "shared_logF": float(lf32[0]), "shared_se": float(lf32[1]),
+                               "se_ratio": float(lind[1] / lf32[1]), "time_ratio": ms_ind / ms_logcdf},
         "accuracy_fp32_vs_fp64": {"logF_fp32": float(lf32[0]), "logF_fp64": float(lf64[0]),
                                   "se_fp64": float(lf64[1]),
                                   "rel_total": abs(lf32[0] - lf64[0]) / abs(lf64[0]),

@@ -83,12 +83,22 @@ typedef struct {
   double nugget;    /* >= 0, added to the diagonal                    */
 } vecchia_cov;
 
+/* vecchia_qmc.flags: estimate each term's numerator and denominator from
+ * separate point sets (the literal reading of Section 2.2, which asks for a QM
+ * estimate of each): the numerator from the term's lattice, the denominator
+ * from a second lattice whose shifts are SplitMix64 outputs key + 2^61. Twice
+ * the QMC work; the two estimates are independent, so
+ * se^2 = [sum_r (n_r/n - 1)^2 + sum_r (d_r/d - 1)^2] / (R (R - 1)) (per-shift
+ * means n_r, d_r). The default (flags = 0) shares one lattice, whose SE is
+ * several times smaller at the same work. */
+#define VECCHIA_QMC_INDEPENDENT 1
+
 typedef struct {
   int32_t n_points;   /* N lattice points per shift, 1..VECCHIA_MAX_POINTS          */
   int32_t n_shifts;   /* R random shifts, 1..VECCHIA_MAX_SHIFTS (R = 1: SE is NaN)  */
   uint64_t seed;      /* keys the random shifts                                     */
   int32_t precision;  /* VECCHIA_FP64 or VECCHIA_FP32_LOOP                          */
-  int32_t reserved;   /* must be 0                                                  */
+  int32_t flags;      /* 0 or VECCHIA_QMC_INDEPENDENT                               */
 } vecchia_qmc;
 
 /* Mixing law of the Gaussian scale mixture X = R W (Section 4, eqs. (7)-(8)):

@@ -561,7 +561,7 @@ vecchia_status vecchia_logcdf(vecchia_plan_t plan, const double* x_dev, double s
   std::lock_guard<std::mutex> lk(plan->mu);
   Batch* b = plan->single.get();
   if (!b || b->qmcs()[0].n_shifts != q->n_shifts || b->qmcs()[0].precision != q->precision ||
-      b->qmcs()[0].n_points != q->n_points ||
+      b->qmcs()[0].n_points != q->n_points || b->qmcs()[0].flags != q->flags ||
       b->chunk_points(0) != chunk_points_for(plan->m, q->precision, q->n_points)) {
     std::unique_ptr<Batch> nb;
     vecchia_status st = Batch::create({plan}, {*q}, &nb);

@@ -3,13 +3,15 @@
 // term_finalize: one wave per term (all instances of a launch). A term with no
 // SOV dimension (k = 0; in a censored plan also a density term or a censored
 // term whose neighbours are all uncensored), or one that term_setup found to be
-// 0 (a -inf limit), takes the exact value term_setup wrote, with SE 0; otherwise the wave's lanes take the
-// shifts (lane r sums shift r's chunks in order), fixed butterflies give the
-// totals, and
+// 0 (a -inf limit), takes the exact value term_setup wrote, with SE 0;
+// otherwise the wave's lanes take the shifts (lane r sums shift r's chunks in
+// order), fixed butterflies give the totals, and
 //     log-term = log(sum_r num_r) - log(sum_r den_r)
 // (with the FP32 loop, log1p(-sum cnum / sum den) when that tail is the smaller,
 // which keeps digits for terms close to 1), and the delta-method standard error
 //     se^2 = R/(R-1) sum_r (num_r / sum num - den_r / sum den)^2   (NaN for R = 1).
+// With independent points (passes = 2) the denominators come from the second
+// lattice's sums and se^2 = R/(R-1) sum_r [(num_r / sum num - 1/R)^2 + (den_r / sum den - 1/R)^2].
 // Results go to a per-term array and, when asked for, to the user-order output.
 //
 // instance_logsum: one block per instance sums its terms' log-terms and se^2 in
@@ -54,17 +56,21 @@ __global__ __launch_bounds__(64 * kFinalizeWaves) void term_finalize(
     se2 = 0.0;
   } else {
     const int C = I.n_chunks;
-    const double* s = sums + 3 * (I.sums_base + i * R * (int64_t)C);
+    const bool indep = I.passes == 2;
+    // numerators from the term's lattice; denominators from the same sums, or
+    // from the second lattice's R x C sums that follow them
+    const double* s = sums + 3 * (I.sums_base + i * I.passes * R * (int64_t)C);
+    const double* sdn = s + (indep ? 3 * (int64_t)R * C : 0);
     double pn = 0.0, pd = 0.0, pc = 0.0;
     for (int r = lane; r < R; r += 64) {
       for (int c = 0; c < C; ++c) {
         pn += s[3 * (r * C + c)];
-        pd += s[3 * (r * C + c) + 1];
+        pd += sdn[3 * (r * C + c) + 1];
         pc += s[3 * (r * C + c) + 2];
       }
     }
     const double sn = wave_sum(pn), sd = wave_sum(pd), sc = wave_sum(pc);
-    if (I.precision == VECCHIA_FP32_LOOP && sc < sn)
+    if (I.precision == VECCHIA_FP32_LOOP && !indep && sc < sn)
       lt = log1p(-sc / sd);
     else
       lt = log(sn) - log(sd);
@@ -74,10 +80,16 @@ __global__ __launch_bounds__(64 * kFinalizeWaves) void term_finalize(
         double nr = 0.0, dr = 0.0;
         for (int c = 0; c < C; ++c) {
           nr += s[3 * (r * C + c)];
-          dr += s[3 * (r * C + c) + 1];
+          dr += sdn[3 * (r * C + c) + 1];
         }
-        const double d = nr / sn - dr / sd;
-        acc += d * d;
+        if (indep) {
+          // independent estimates: their relative variances add
+          const double a = nr / sn - 1.0 / R, b = dr / sd - 1.0 / R;
+          acc += a * a + b * b;
+        } else {
+          const double d = nr / sn - dr / sd;
+          acc += d * d;
+        }
       }
       se2 = wave_sum(acc) * (double)R / (double)(R - 1);
     } else {

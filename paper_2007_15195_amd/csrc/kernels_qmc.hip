@@ -54,7 +54,9 @@ struct Item {
   const InstDesc* I;
   int64_t i;      // plan index of the term
   int64_t t;      // global term index
-  int r;          // shift
+  int r;          // pass * n_shifts + shift: the item's slot among the term's shifts
+  int sr;         // shift
+  bool second;    // pass 1: the term's second lattice (independent-points estimator)
   int c;          // chunk
   int K;
 };
@@ -73,6 +75,9 @@ __device__ __forceinline__ Item decode_item(const InstDesc* __restrict__ insts,
   it.i = R.term_begin + term_off;
   it.r = uniform(rem / R.n_chunks);
   it.c = uniform(rem - it.r * R.n_chunks);
+  const int ns = uniform(it.I->n_shifts);
+  it.second = it.r >= ns;
+  it.sr = it.second ? it.r - ns : it.r;
   it.K = uniform(R.K);
   it.t = it.I->term_base + it.i;
   return it;
@@ -84,7 +89,7 @@ __device__ __forceinline__ Item decode_item(const InstDesc* __restrict__ insts,
 // and up to 1.3x (FP32) / 2.4x (FP64) faster for large K, whose rows no longer
 // fit the vector L1 beside the other resident waves.
 __device__ __forceinline__ double* item_out(const InstDesc& I, const Item& it, double* sums) {
-  return sums + 3 * (I.sums_base + (it.i * I.n_shifts + it.r) * (int64_t)I.n_chunks + it.c);
+  return sums + 3 * (I.sums_base + (it.i * I.passes * I.n_shifts + it.r) * (int64_t)I.n_chunks + it.c);
 }
 
 // Out-of-line double-precision normal CDF and quantile (HIP device library),
@@ -106,7 +111,7 @@ __device__ __forceinline__ void item_f64(const Item& it, const Aux64* __restrict
   uint64_t U[K];
 #pragma unroll
   for (int j = 0; j < K; ++j)
-    U[j] = (uint64_t)(p_begin + lane) * Zg[j] + lattice_shift(I.seed, it.i, it.r, j);
+    U[j] = (uint64_t)(p_begin + lane) * Zg[j] + lattice_shift(I.seed, it.i, it.sr, j, it.second);
   constexpr int kRowElems = (K + 1) * (K + 2) / 2;   // rows 0..K of the term's block
   __shared__ double srow[kRowElems];
   for (int e = lane; e < kRowElems; e += 64) srow[e] = prep[e];
@@ -185,7 +190,7 @@ __device__ __forceinline__ void item_f32(const Item& it, const Aux32* __restrict
   uint64_t U[K];
 #pragma unroll
   for (int j = 0; j < K; ++j) {
-    const uint64_t S = lattice_shift(I.seed, it.i, it.r, j);
+    const uint64_t S = lattice_shift(I.seed, it.i, it.sr, j, it.second);
     U[j] = (uint64_t)(p_begin + lane) * Zg[j] + S;
   }
   constexpr int kRowElems = (K + 1) * (K + 2) / 2;   // rows 0..K of the term's block
@@ -323,7 +328,7 @@ __device__ __forceinline__ void item_f32_gen(const Item& it, const Aux32* __rest
   const int p_last = min(I.n_points, p_begin + I.chunk_points - 1);
   const int rows = (K + 1) * (K + 2) / 2;
   for (int e = lane; e < rows; e += 64) srow[e] = prep[e];
-  for (int j = lane; j < K; j += 64) sh[j] = lattice_shift(I.seed, it.i, it.r, j);
+  for (int j = lane; j < K; j += 64) sh[j] = lattice_shift(I.seed, it.i, it.sr, j, it.second);
   __syncthreads();
   double acc_num = 0.0, acc_den = 0.0, acc_cnum = 0.0;
   for (int p0 = p_begin; p0 <= p_last; p0 += 64) {
@@ -441,7 +446,7 @@ __device__ __forceinline__ void item_f64_gen(const Item& it, const Aux64* __rest
   const int p_last = min(I.n_points, p_begin + I.chunk_points - 1);
   const int rows = (K + 1) * (K + 2) / 2;
   for (int e = lane; e < rows; e += 64) srow[e] = prep[e];
-  for (int j = lane; j < K; j += 64) sh[j] = lattice_shift(I.seed, it.i, it.r, j);
+  for (int j = lane; j < K; j += 64) sh[j] = lattice_shift(I.seed, it.i, it.sr, j, it.second);
   __syncthreads();
   double acc_num = 0.0, acc_den = 0.0;
   for (int p0 = p_begin; p0 <= p_last; p0 += 64) {

@@ -24,9 +24,12 @@ __device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t n) {
 
 // Dimensions 32..62 (terms of more than 32 variables) take the key
 // 2^62 + (term << 22) + (shift << 6) + dim, a range the first form never reaches.
-__device__ __forceinline__ uint64_t lattice_shift(uint64_t seed, int64_t term, int r, int dim) {
-  if (dim < 32) return splitmix64(seed, ((uint64_t)term << 21) | ((uint64_t)r << 5) | (uint64_t)dim);
-  return splitmix64(seed, (1ULL << 62) | ((uint64_t)term << 22) | ((uint64_t)r << 6) | (uint64_t)dim);
+// A term's second lattice (the denominators of the independent-points
+// estimator) adds 2^61 to the key: no first-lattice key has that bit set.
+__device__ __forceinline__ uint64_t lattice_shift(uint64_t seed, int64_t term, int r, int dim, bool second) {
+  const uint64_t salt = second ? (1ULL << 61) : 0ULL;
+  if (dim < 32) return splitmix64(seed, salt | ((uint64_t)term << 21) | ((uint64_t)r << 5) | (uint64_t)dim);
+  return splitmix64(seed, salt | (1ULL << 62) | ((uint64_t)term << 22) | ((uint64_t)r << 6) | (uint64_t)dim);
 }
 
 // FP64 coordinate (2 floor(W / 2^12) + 1) 2^-53.

@@ -134,7 +134,7 @@ void rule_for(const vecchia_mixture& m, double lo, double hi, double* v, double*
 vecchia_status ensure_batch(vecchia_plan_s* P, std::unique_ptr<Batch>* slot, int n, const vecchia_qmc& q) {
   Batch* b = slot->get();
   if (b && b->n() == n && b->qmcs()[0].n_shifts == q.n_shifts && b->qmcs()[0].precision == q.precision &&
-      b->qmcs()[0].n_points == q.n_points && b->chunk_points(0) == chunk_points_for(P->m, q.precision, q.n_points))
+      b->qmcs()[0].n_points == q.n_points && b->qmcs()[0].flags == q.flags && b->chunk_points(0) == chunk_points_for(P->m, q.precision, q.n_points))
     return VECCHIA_OK;
   std::unique_ptr<Batch> nb;
   vecchia_status st = Batch::create(std::vector<vecchia_plan_s*>(n, P), std::vector<vecchia_qmc>(n, q), &nb);

@@ -182,6 +182,10 @@ bool valid_qmc(const vecchia_qmc& q, std::string* why) {
     *why = "precision must be VECCHIA_FP64 or VECCHIA_FP32_LOOP";
     return false;
   }
+  if (q.flags != 0 && q.flags != VECCHIA_QMC_INDEPENDENT) {
+    *why = "flags must be 0 or VECCHIA_QMC_INDEPENDENT";
+    return false;
+  }
   return true;
 }
 
@@ -256,6 +260,7 @@ vecchia_status Batch::create(const std::vector<vecchia_plan_s*>& plans,
     if (P->device != dev) return set_error(VECCHIA_E_INVALID, "plan belongs to another device");
     if (!valid_qmc(qmcs[j], &why)) return set_error(VECCHIA_E_INVALID, "instance " + std::to_string(j) + ": " + why);
     const int R = qmcs[j].n_shifts;
+    const int passes = qmcs[j].flags == VECCHIA_QMC_INDEPENDENT ? 2 : 1;   // a second lattice for the denominators
     const int prec = qmcs[j].precision;
     const int nv = P->block > 0 ? P->block_nv : P->m + 1;   // variables per term, at most
     const int stride = (int)align_up((size_t)nv * (nv + 1) / 2, prec == VECCHIA_FP32_LOOP ? 4 : 2);
@@ -279,6 +284,7 @@ vecchia_status Batch::create(const std::vector<vecchia_plan_s*>& plans,
     d.m = P->m;
     d.n_points = qmcs[j].n_points;
     d.n_shifts = R;
+    d.passes = passes;
     d.seed = qmcs[j].seed;
     d.prep_stride = stride;
     d.precision = prec;
@@ -303,16 +309,16 @@ vecchia_status Batch::create(const std::vector<vecchia_plan_s*>& plans,
         r.term_begin = i;
         r.inst = j;
         r.K = k;
-        r.items_per_term = R * C;
+        r.items_per_term = passes * R * C;
         r.n_chunks = C;
         by_k[{k, prec, P->block > 0}].push_back(r);
       }
       i = e;
     }
-    if ((int64_t)R * C > 0x7fffffffLL / std::max<int64_t>(1, NT))
+    if ((int64_t)passes * R * C > 0x7fffffffLL / std::max<int64_t>(1, NT))
       return set_error(VECCHIA_E_INVALID, "instance " + std::to_string(j) + " has more than 2^31 work items");
     tb += NT;
-    sb += NT * (int64_t)R * C;
+    sb += NT * (int64_t)passes * R * C;
   }
   b->term_bases_[n] = tb;
   b->total_terms_ = tb;
@@ -334,7 +340,8 @@ vecchia_status Batch::create(const std::vector<vecchia_plan_s*>& plans,
       const int64_t nterms = r.item_begin;
       r.item_begin = items;
       items += nterms * r.items_per_term;
-      L.sov_steps += nterms * (int64_t)b->desc_[r.inst].n_shifts * b->desc_[r.inst].n_points * r.K;
+      L.sov_steps += nterms * (int64_t)b->desc_[r.inst].passes * b->desc_[r.inst].n_shifts *
+                     b->desc_[r.inst].n_points * r.K;
       b->ranges_.push_back(r);
     }
     L.n_items = items;

@@ -47,6 +47,8 @@ struct InstDesc {
   int32_t family;          // VECCHIA_COV_*
   int32_t m;
   int32_t n_points, n_shifts;
+  int32_t passes;          // 2: the denominators come from a second lattice (VECCHIA_QMC_INDEPENDENT)
+  int32_t pad_;
   uint64_t seed;
   int32_t prep_stride;     // elements per term in prep
   int32_t precision;       // VECCHIA_FP64 / VECCHIA_FP32_LOOP
@@ -55,14 +57,14 @@ struct InstDesc {
 };
 
 // A contiguous run of terms with the same K inside one instance. Its work items
-// are (term, shift, chunk) triples, n_terms * n_shifts * n_chunks of them, in
-// that nesting order.
+// are (term, pass, shift, chunk), n_terms * passes * n_shifts * n_chunks of
+// them, in that nesting order.
 struct RangeDesc {
   int64_t item_begin;      // exclusive prefix of items over the ranges of a launch
   int64_t term_begin;      // plan index of the first term
   int32_t inst;            // instance index
   int32_t K;               // conditioning-set size of every term of the range
-  int32_t items_per_term;  // n_shifts * n_chunks
+  int32_t items_per_term;  // passes * n_shifts * n_chunks
   int32_t n_chunks;
 };
 

@@ -23,7 +23,8 @@ STATUS_NAMES = {0: "OK", 1: "E_INVALID", 2: "E_NOMEM", 3: "E_NOT_PD", 4: "E_HIP"
 VECCHIA_ORDER_GIVEN, VECCHIA_ORDER_COORD, VECCHIA_ORDER_MAXMIN = 0, 1, 2
 VECCHIA_COV_EXPONENTIAL, VECCHIA_COV_MATERN = 0, 1
 VECCHIA_FP64, VECCHIA_FP32_LOOP = 0, 1
-VECCHIA_MAX_M = 31
+VECCHIA_MAX_M = 63
+VECCHIA_QMC_INDEPENDENT = 1
 
 EXPORTED = [
     "vecchia_last_error", "vecchia_order", "vecchia_plan", "vecchia_plan_from_cov",
@@ -57,7 +58,7 @@ class vecchia_mixture(ctypes.Structure):
 
 class vecchia_qmc(ctypes.Structure):
     _fields_ = [("n_points", c_int32), ("n_shifts", c_int32), ("seed", c_uint64),
-                ("precision", c_int32), ("reserved", c_int32)]
+                ("precision", c_int32), ("flags", c_int32)]
 
 
 _lib = None
@@ -158,8 +159,11 @@ def make_cov(family=VECCHIA_COV_MATERN, nu=0.5, sigma2=1.0, range=0.1, nugget=0.
     return vecchia_cov(int(family), 0, float(nu), float(sigma2), float(range), float(nugget))
 
 
-def make_qmc(n_points=1000, n_shifts=10, seed=1, precision=VECCHIA_FP64) -> vecchia_qmc:
-    return vecchia_qmc(int(n_points), int(n_shifts), int(seed) & (2 ** 64 - 1), int(precision), 0)
+def make_qmc(n_points=1000, n_shifts=10, seed=1, precision=VECCHIA_FP64, independent=False) -> vecchia_qmc:
+    """QMC settings; independent: separate point sets for each term's numerator
+    and denominator (VECCHIA_QMC_INDEPENDENT)."""
+    return vecchia_qmc(int(n_points), int(n_shifts), int(seed) & (2 ** 64 - 1), int(precision),
+                       VECCHIA_QMC_INDEPENDENT if independent else 0)
 
 
 def as_cov(c) -> vecchia_cov:
@@ -171,7 +175,7 @@ def as_cov(c) -> vecchia_cov:
 def as_qmc(q) -> vecchia_qmc:
     if isinstance(q, vecchia_qmc):
         return q
-    return make_qmc(q.n_points, q.n_shifts, q.seed, q.precision)
+    return make_qmc(q.n_points, q.n_shifts, q.seed, q.precision, getattr(q, "independent", False))
 
 
 # ----------------------------------------------------------------- entry points

@@ -257,3 +257,20 @@ def test_block_plan_arguments_rejected_on_the_host():
     for terms in ([([0, 1], 2)], [([0, 0], 1)], [([0, 5], 1)], [([], 0)], [(list(range(4)), -1)]):
         with pytest.raises(V.VecchiaError):
             V.vecchia_plan_from_cov_block(S, terms, stream=0)
+
+
+def test_binding_constants_match_the_header():
+    import re
+    from paper_2007_15195_amd import vecchia as V
+    hdr = open(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include",
+                            "vecchia.h")).read()
+    defines = dict(re.findall(r"#define (VECCHIA_[A-Z0-9_]+) (\d+)", hdr))
+    checked = 0
+    for name, val in defines.items():
+        if hasattr(V, name):
+            assert getattr(V, name) == int(val), name
+            checked += 1
+    assert checked >= 2
+    assert V.MIX_SEARCH_NODES == int(defines["VECCHIA_MIX_SEARCH_NODES"])
+    assert V.make_qmc(64, 2, 1, V.VECCHIA_FP32_LOOP, independent=True).flags == V.VECCHIA_QMC_INDEPENDENT
+
