@@ -31,10 +31,14 @@ void free_plan_buffers(vecchia_plan_s* P) {
     if (P->replan_ev[k]) hipEventDestroy(P->replan_ev[k]);
     if (P->h_replan[k]) hipHostFree(P->h_replan[k]);
   }
-  hipFree(P->d_xs);
-  hipFree(P->d_ys);
+  if (P->d_geo) {
+    hipFree(P->d_geo);   // holds d_xs, d_ys and d_perm
+  } else {
+    hipFree(P->d_xs);
+    hipFree(P->d_ys);
+    hipFree(P->d_perm);
+  }
   hipFree(P->d_cov);
-  hipFree(P->d_perm);
   hipFree(P->d_nbr);
   hipFree(P->d_kcnt);
   hipFree(P->d_sovk);
@@ -209,26 +213,31 @@ vecchia_status build_geometry_plan(const double* locs_host, int64_t D, std::vect
   P->n_obs = n_obs;
   P->n_terms = D;
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  std::vector<double> hx(D), hy(D);
-  std::vector<int32_t> hp(D);
+  // {xs, ys, perm} packed as the device block (and the replan staging)
+  const size_t geo_bytes = (sizeof(double) * 2 + sizeof(int32_t)) * (size_t)D;
+  std::vector<char> geo(geo_bytes);
+  double* hx = reinterpret_cast<double*>(geo.data());
+  double* hy = hx + D;
+  int32_t* hp = reinterpret_cast<int32_t*>(hy + D);
   for (int64_t i = 0; i < D; ++i) {
     hx[i] = locs_host[2 * P->perm[i]];
     hy[i] = locs_host[2 * P->perm[i] + 1];
     hp[i] = (int32_t)P->perm[i];
   }
-  hipError_t e = dev_alloc(&P->d_xs, D);
-  if (e == hipSuccess) e = dev_alloc(&P->d_ys, D);
-  if (e == hipSuccess) e = dev_alloc(&P->d_perm, D);
+  hipError_t e = hipMalloc(&P->d_geo, geo_bytes);
+  if (e == hipSuccess) {
+    P->d_xs = static_cast<double*>(P->d_geo);
+    P->d_ys = P->d_xs + D;
+    P->d_perm = reinterpret_cast<int32_t*>(P->d_ys + D);
+  }
   if (e == hipSuccess) e = dev_alloc(&P->d_kcnt, D);
   if (e == hipSuccess && n_obs > 0) e = dev_alloc(&P->d_sovk, D);
   if (e == hipSuccess && m > 0) e = dev_alloc(&P->d_nbr, (size_t)D * m);
   if (e == hipSuccess && m > 0 && D > kKnnGridMinD && group == 1) {
     e = alloc_grid(P);
-    grid_geometry(hx.data(), hy.data(), D, &P->grid);
+    grid_geometry(hx, hy, D, &P->grid);
   }
-  if (e == hipSuccess) e = hipMemcpyAsync(P->d_xs, hx.data(), sizeof(double) * D, hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = hipMemcpyAsync(P->d_ys, hy.data(), sizeof(double) * D, hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = hipMemcpyAsync(P->d_perm, hp.data(), sizeof(int32_t) * D, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(P->d_geo, geo.data(), geo_bytes, hipMemcpyHostToDevice, s);
   if (e == hipSuccess)
     e = launch_knn(P->d_xs, P->d_ys, D, m, P->d_nbr, P->d_kcnt, P->has_grid ? &P->grid : nullptr, s, group);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -521,9 +530,8 @@ vecchia_status vecchia_replan(vecchia_plan_t plan, const double* locs_host, int3
     hy[i] = locs_host[2 * perm[i] + 1];
     hp[i] = (int32_t)perm[i];
   }
-  e = hipMemcpyAsync(plan->d_xs, hx, sizeof(double) * D, hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = hipMemcpyAsync(plan->d_ys, hy, sizeof(double) * D, hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = hipMemcpyAsync(plan->d_perm, hp, sizeof(int32_t) * D, hipMemcpyHostToDevice, s);
+  // the staging block has the device block's layout: one copy
+  e = hipMemcpyAsync(plan->d_geo, hx, (sizeof(double) * 2 + sizeof(int32_t)) * (size_t)D, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipEventRecord(plan->replan_ev[k], s);
   if (plan->has_grid) grid_geometry(hx, hy, D, &plan->grid);
   if (e == hipSuccess)

@@ -164,6 +164,9 @@ struct vecchia_plan_s {
   int32_t* d_split = nullptr;
   const std::vector<int32_t>& sov_dims() const { return (n_obs > 0 || block > 0) ? sovk : kcnt; }
   int64_t terms() const { return block > 0 ? n_terms : D; }
+  // geometry plans keep {xs, ys (D doubles each), perm (D int32)} in one
+  // allocation, d_geo, laid out as the replan staging, so one copy moves them
+  void* d_geo = nullptr;
   double* d_xs = nullptr;
   double* d_ys = nullptr;
   double* d_cov = nullptr;
