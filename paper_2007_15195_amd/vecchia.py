@@ -24,6 +24,8 @@ VECCHIA_ORDER_GIVEN, VECCHIA_ORDER_COORD, VECCHIA_ORDER_MAXMIN = 0, 1, 2
 VECCHIA_COV_EXPONENTIAL, VECCHIA_COV_MATERN = 0, 1
 VECCHIA_FP64, VECCHIA_FP32_LOOP = 0, 1
 VECCHIA_MAX_M = 63
+VECCHIA_MAX_SHIFTS = 65536
+VECCHIA_MAX_POINTS = 1 << 30
 VECCHIA_QMC_INDEPENDENT = 1
 
 EXPORTED = [

@@ -152,3 +152,47 @@ def test_mixture_of_a_minus_inf_threshold_is_minus_inf():
     got = out.cpu().numpy()
     assert got[0] == -math.inf and got[1] == 0.0
     V.vecchia_plan_destroy(plan)
+
+
+@pytest.mark.parametrize("prec", [W.PREC_FP64, W.PREC_FP32])
+def test_largest_point_count_against_the_closed_form(prec):
+    # N = VECCHIA_MAX_POINTS = 2^30 lattice points: 2^19..2^21 work items for one
+    # bivariate term, whose value is Owen's closed form
+    torch = torch_cuda()
+    from paper_2007_15195_amd import vecchia as V
+    from tests import closed_forms as cf
+    rho = 0.6
+    S = np.array([[1.0, rho], [rho, 1.0]])
+    b = np.array([0.4, -0.3])
+    plan = V.vecchia_plan_from_cov(S, 1)
+    x = torch.tensor(b, dtype=torch.float64, device="cuda")
+    out = torch.empty(2, dtype=torch.float64, device="cuda")
+    terms = torch.empty((2, 2), dtype=torch.float64, device="cuda")
+    V.vecchia_logcdf(plan, x, V.make_qmc(V.VECCHIA_MAX_POINTS, 2, 3, prec), out, terms=terms)
+    torch.cuda.synchronize()
+    V.vecchia_plan_destroy(plan)
+    t = terms.cpu().numpy()
+    want = math.log(cf.bivariate_owen(b[0], b[1], rho))
+    tol = 1e-9 if prec == W.PREC_FP64 else 1e-6
+    assert abs(out.cpu().numpy()[0] - want) <= tol, (out.cpu().numpy(), want)
+    assert t[1, 1] < 1e-6
+
+
+def test_largest_shift_count_matches_the_oracle():
+    # R = VECCHIA_MAX_SHIFTS = 65536 shifts of 64 points: the finalize's per-lane
+    # loops over shifts and its SE at their longest
+    torch = torch_cuda()
+    from paper_2007_15195_amd import vecchia as V
+    S = np.array([[1.0, 0.45], [0.45, 1.0]])
+    b = np.array([0.2, 0.9])
+    plan = V.vecchia_plan_from_cov(S, 1)
+    x = torch.tensor(b, dtype=torch.float64, device="cuda")
+    out = torch.empty(2, dtype=torch.float64, device="cuda")
+    terms = torch.empty((2, 2), dtype=torch.float64, device="cuda")
+    V.vecchia_logcdf(plan, x, V.make_qmc(64, V.VECCHIA_MAX_SHIFTS, 5, V.VECCHIA_FP64), out, terms=terms)
+    torch.cuda.synchronize()
+    V.vecchia_plan_destroy(plan)
+    o = oracle.logcdf_from_cov(S, b, [[], [0]], 64, V.VECCHIA_MAX_SHIFTS, 5)
+    t = terms.cpu().numpy()
+    assert np.max(np.abs(t[:, 0] - o["terms"][:, 0])) <= 1e-10
+    np.testing.assert_allclose(t[:, 1], o["terms"][:, 1], rtol=1e-6, atol=1e-14)
