@@ -274,3 +274,17 @@ def test_binding_constants_match_the_header():
     assert V.MIX_SEARCH_NODES == int(defines["VECCHIA_MIX_SEARCH_NODES"])
     assert V.make_qmc(64, 2, 1, V.VECCHIA_FP32_LOOP, independent=True).flags == V.VECCHIA_QMC_INDEPENDENT
 
+
+
+def test_empty_inputs_are_rejected_before_gpu_work():
+    cov = V.make_cov(V.VECCHIA_COV_MATERN, 1.5, 1.0, 0.1, 0.0)
+    none = np.zeros((0, 2))
+    calls = [lambda: V.vecchia_order(none, W.ORDER_COORD),
+             lambda: V.vecchia_plan(none, W.ORDER_COORD, 2, cov, stream=0),
+             lambda: V.vecchia_plan_from_cov(np.zeros((0, 0)), 0, stream=0),
+             lambda: V.vecchia_plan_block(none, W.ORDER_COORD, 2, 2, cov, stream=0),
+             lambda: V.vecchia_plan_censored(none, np.zeros(0, dtype=bool), W.ORDER_COORD, 2, cov, stream=0)]
+    for f in calls:
+        with pytest.raises(V.VecchiaError) as e:
+            f()
+        assert e.value.status == 1
