@@ -411,6 +411,38 @@ vecchia_status vecchia_tuning_set(int32_t precision, int32_t m, int32_t chunk_po
  * (rates_out NULL), HIP. */
 vecchia_status vecchia_calibrate_valu(void* hip_stream, double* rates_out);
 
+/* Test hooks: the device's own normal CDF and quantile pieces (Section 2.2's
+ * univariate Phi and Phi^{-1} inside Genz's recursion), evaluated elementwise
+ * so that tests pin them against library routines. in_dev: n doubles;
+ * out_dev: n x 3 doubles {o0, o1, o2} (device). what:
+ *   VECCHIA_PROBE_PHI_F32: the FP32 loop's factor at t = in: o0 = Phi(-|t|) as
+ *     the main path forms it (2^(-v^2) R, v = kappa t in FP32), and the deep
+ *     path's split o1 * 2^o2 of the same tail;
+ *   VECCHIA_PROBE_NINV_F32: o0 = -Phi^{-1}(q) as the loop forms it from
+ *     log2 q, q = in rounded to FP32 (0 < q <= 1/2), o1 = that q;
+ *   VECCHIA_PROBE_NINV_LOG2_F32: o0 = -Phi^{-1}(2^in) from the FP32 log2 in
+ *     (the split path, whose exponents reach -2^20);
+ *   VECCHIA_PROBE_PHI_F64 / VECCHIA_PROBE_NINV_F64: o0 = the FP64 loop's
+ *     normcdf(in) / normcdfinv(in).
+ * Asynchronous on hip_stream. Errors: INVALID (unknown what, n outside
+ * 0..2^30, null pointers), HIP. */
+#define VECCHIA_PROBE_PHI_F32 0
+#define VECCHIA_PROBE_NINV_F32 1
+#define VECCHIA_PROBE_NINV_LOG2_F32 2
+#define VECCHIA_PROBE_PHI_F64 3
+#define VECCHIA_PROBE_NINV_F64 4
+vecchia_status vecchia_probe_math(int32_t what, int64_t n, const double* in_dev, double* out_dev,
+                                  void* hip_stream);
+
+/* Test hook: the lattice coordinates p = 1..n of dimension dim (0..62) in
+ * shift `shift` of plan-order term `term`, as the QMC kernels form them
+ * (the randomized Richtmyer rule with its SplitMix64 shift; second = 1 for the
+ * term's second lattice): w64_dev (n doubles, FP64 coordinates) and w32_dev
+ * (n floats, FP32 coordinates), either may be NULL. Asynchronous on
+ * hip_stream. Errors: INVALID (arguments out of range), HIP. */
+vecchia_status vecchia_probe_lattice(uint64_t seed, int64_t term, int32_t shift, int32_t dim, int32_t second,
+                                     int64_t n, double* w64_dev, float* w32_dev, void* hip_stream);
+
 /* Serving: a request loop with continuous batching. Requests are admitted in
  * arrival order while their workspace fits in hbm_budget_bytes and one of
  * max_slots execution slots (each its own stream) is free; admitted requests

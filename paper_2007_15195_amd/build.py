@@ -34,6 +34,7 @@ SOURCES = [
     "calibrate.hip",
     "mixture.cpp",
     "fullsov.hip",
+    "probe.hip",
 ]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-function",

@@ -39,7 +39,7 @@ EXPORTED = [
     "vecchia_plan_censored", "vecchia_plan_from_cov_censored", "vecchia_plan_censoring",
     "vecchia_mixbatch_create", "vecchia_mixbatch_logcdf", "vecchia_mixbatch_status", "vecchia_mixbatch_destroy",
     "vecchia_map_anisotropic", "vecchia_plan_block", "vecchia_plan_block_terms", "vecchia_plan_from_cov_block",
-    "vecchia_full_logcdf",
+    "vecchia_full_logcdf", "vecchia_probe_math", "vecchia_probe_lattice",
 ]
 
 
@@ -121,6 +121,9 @@ def lib():
         "vecchia_tuning_get": [c_int32, c_int32, POINTER(c_int32)],
         "vecchia_tuning_set": [c_int32, c_int32, c_int32],
         "vecchia_calibrate_valu": [c_void_p, c_void_p],
+        "vecchia_probe_math": [c_int32, c_int64, c_void_p, c_void_p, c_void_p],
+        "vecchia_probe_lattice": [c_uint64, c_int64, c_int32, c_int32, c_int32, c_int64, c_void_p, c_void_p,
+                                  c_void_p],
         "vecchia_mixture_logcdf": [c_void_p, c_void_p, POINTER(vecchia_mixture), c_void_p, POINTER(vecchia_qmc),
                                    c_void_p, c_void_p, c_void_p],
         "vecchia_mixture_rule": [POINTER(vecchia_mixture), c_void_p, c_void_p, c_void_p, c_void_p, c_void_p],
@@ -419,6 +422,32 @@ def vecchia_calibrate_valu(stream=None) -> dict:
     r = (c_double * 5)()
     _check(lib().vecchia_calibrate_valu(_stream_ptr(stream), ctypes.cast(r, c_void_p)))
     return dict(zip(("fma", "exp", "log", "rcp", "sqrt"), list(r)))
+
+
+VECCHIA_PROBE_PHI_F32, VECCHIA_PROBE_NINV_F32, VECCHIA_PROBE_NINV_LOG2_F32 = 0, 1, 2
+VECCHIA_PROBE_PHI_F64, VECCHIA_PROBE_NINV_F64 = 3, 4
+
+
+def vecchia_probe_math(what: int, x, out, stream=None) -> None:
+    """Device normal CDF / quantile pieces at x (float64 CUDA tensor); out: n x 3."""
+    n = x.numel()
+    _check(lib().vecchia_probe_math(int(what), n, _dev_ptr(x, n, "x"), _dev_ptr(out, 3 * n, "out"),
+                                    _stream_ptr(stream)))
+
+
+def vecchia_probe_lattice(seed: int, term: int, shift: int, dim: int, second: bool, n: int, w64=None, w32=None,
+                          stream=None) -> None:
+    """Lattice coordinates p = 1..n as the kernels form them (FP64 into w64, FP32 into w32)."""
+    import torch
+    p64 = None if w64 is None else _dev_ptr(w64, n, "w64")
+    p32 = None
+    if w32 is not None:
+        if not (isinstance(w32, torch.Tensor) and w32.is_cuda and w32.dtype == torch.float32 and
+                w32.is_contiguous() and w32.numel() >= n):
+            raise ValueError("w32 must be a contiguous float32 CUDA tensor of n values")
+        p32 = w32.data_ptr()
+    _check(lib().vecchia_probe_lattice(int(seed) & (2 ** 64 - 1), int(term), int(shift), int(dim),
+                                       1 if second else 0, int(n), p64, p32, _stream_ptr(stream)))
 
 
 MIX_SEARCH_NODES = 24

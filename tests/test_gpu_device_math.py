@@ -1,0 +1,105 @@
+"""Unit pins of the device pieces through the test hooks: the FP32 loop's
+normal tail and quantile and the FP64 loop's normcdf / normcdfinv against
+SciPy (ndtr, log_ndtr, ndtri, ndtri_exp) on a million points each, tails
+included; and the lattice coordinates against the oracle's exact integer
+definition, bit for bit (FP64 and FP32, both lattices of a term, the key
+ranges' edges). The error figures are printed.
+
+Bounds: the FP32 tail's relative error is the rational's (< 1.4e-6) plus the
+rounding of the exponent -v^2 in FP32 (up to 2^-24 |v^2|, i.e. ln 2 v^2 2^-24
+relative); the FP32 quantile's is the rational's within its fitted range
+s = sqrt(-log2 q) <= 34 and grows slowly beyond it (the split path's
+exponents, q < 2^-1156); FP64 is HIP's library (relative errors of a few
+1e-13 in the far lower tail)."""
+import math
+
+import numpy as np
+import pytest
+from scipy.special import log_ndtr, ndtr, ndtri, ndtri_exp
+
+from oracle import lattice
+from tests.gpu_helpers import torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+KAPPA = math.sqrt(1.0 / (2.0 * math.log(2.0)))
+LN2 = math.log(2.0)
+
+
+def _probe(V, torch, what, x_np):
+    x = torch.tensor(x_np, dtype=torch.float64, device="cuda")
+    out = torch.empty((len(x_np), 3), dtype=torch.float64, device="cuda")
+    V.vecchia_probe_math(what, x, out)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def test_fp32_normal_tail_main_and_split_paths():
+    torch = torch_cuda()
+    from paper_2007_15195_amd import vecchia as V
+    t = np.concatenate([np.linspace(-13.0, 13.0, 600_000), np.linspace(-1000.0, -9.0, 400_000)])
+    o = _probe(V, torch, V.VECCHIA_PROBE_PHI_F32, t)
+    v = (t * KAPPA).astype(np.float32).astype(np.float64)     # the FP32 argument the loop sees
+    te = -np.abs(v) / KAPPA
+    # exponent rounding: f = -v^2 in FP32 carries up to 2^-24 |f| absolute
+    bound = 2.0e-6 + 2.0 * LN2 * v * v * 2.0 ** -24
+    main = np.abs(v) <= 11.0                                   # 2^(-v^2) normal in FP32
+    rel = np.abs(o[main, 0] / ndtr(te[main]) - 1.0)
+    split = np.log(o[:, 1]) + o[:, 2] * LN2 - log_ndtr(te)
+    print("FP32 tail: main path max rel %.2e, split path max |log err| %.2e" % (rel.max(), np.abs(split).max()))
+    assert np.all(rel <= bound[main])
+    assert np.all(np.abs(split) <= bound)
+
+
+def test_fp32_quantile_from_q_and_from_its_log():
+    torch = torch_cuda()
+    from paper_2007_15195_amd import vecchia as V
+    q = np.concatenate([np.logspace(-37.5, math.log10(0.5), 900_000), np.linspace(0.3, 0.5, 100_000)])
+    o = _probe(V, torch, V.VECCHIA_PROBE_NINV_F32, q)
+    want = -ndtri(o[:, 1])                                     # at the FP32 q the loop sees
+    err = np.abs(o[:, 0] - want)
+    print("FP32 quantile: max abs err %.2e, max rel %.2e" % (err.max(), (err / np.maximum(want, 0.05)).max()))
+    assert np.all(err <= 4e-6 * np.maximum(want, 0.05) + 1e-6)
+    lq = -np.logspace(0.0, math.log10(1048576.0 + 126.0), 200_000)
+    o = _probe(V, torch, V.VECCHIA_PROBE_NINV_LOG2_F32, lq)
+    lqf = lq.astype(np.float32).astype(np.float64)
+    want = -ndtri_exp(lqf * LN2)
+    rel = np.abs(o[:, 0] - want) / np.maximum(want, 0.05)
+    fit = -lqf <= 34.0 ** 2             # the rational's fitted range, s = sqrt(-log2 q) <= 34
+    print("FP32 quantile from log2 q: max rel %.2e for q >= 2^-1156, %.2e beyond (to 2^-1048702)"
+          % (rel[fit].max(), rel[~fit].max()))
+    assert np.all(rel[fit] <= 5e-6)
+    assert np.all(rel[~fit] <= 5e-5)
+
+
+def test_fp64_library_pieces():
+    torch = torch_cuda()
+    from paper_2007_15195_amd import vecchia as V
+    x = np.linspace(-37.5, 8.2, 1_000_000)
+    o = _probe(V, torch, V.VECCHIA_PROBE_PHI_F64, x)
+    rel = np.abs(o[:, 0] / ndtr(x) - 1.0)
+    print("FP64 normcdf: max rel %.2e" % rel.max())
+    assert rel.max() <= 1e-12
+    u = np.concatenate([np.logspace(-307, -1, 800_000), np.linspace(0.1, 1.0 - 2.0 ** -53, 200_000)])
+    o = _probe(V, torch, V.VECCHIA_PROBE_NINV_F64, u)
+    want = ndtri(u)
+    err = np.abs(o[:, 0] - want) / np.maximum(np.abs(want), 1.0)
+    print("FP64 normcdfinv: max rel %.2e" % err.max())
+    assert err.max() <= 1e-12
+
+
+@pytest.mark.parametrize("seed,term,shift,dim,second", [
+    (1, 0, 0, 0, False), (0x5EED5EED5EED, 12345, 7, 5, False), (2 ** 64 - 1, 2 ** 31 - 1, 65535, 31, False),
+    (77, 3, 2, 32, False), (77, 3, 2, 62, False), (77, 3, 2, 1, True), (9, 2 ** 31 - 1, 65535, 62, True),
+])
+def test_lattice_coordinates_bit_for_bit(seed, term, shift, dim, second):
+    torch = torch_cuda()
+    from paper_2007_15195_amd import vecchia as V
+    n = 1 << 18
+    w64 = torch.empty(n, dtype=torch.float64, device="cuda")
+    w32 = torch.empty(n, dtype=torch.float32, device="cuda")
+    V.vecchia_probe_lattice(seed, term, shift, dim, second, n, w64, w32)
+    torch.cuda.synchronize()
+    S = lattice.shift(seed, term, shift, dim, second)
+    assert np.array_equal(w64.cpu().numpy(), lattice.points(n, dim, S))
+    assert np.array_equal(w32.cpu().numpy().astype(np.float64), lattice.points(n, dim, S, fp32=True))
