@@ -116,9 +116,18 @@ def cpu_baseline(inst, n_terms):
                   terms_subset=sub, plan_cache=(perm, nbrs), processes=procs)
     t_terms = time.perf_counter() - t0
     t_full = t_plan + t_terms * inst.D / len(sub)
+    # one core: a smaller seeded sample in this process
+    sub1 = sub[:max(1, len(sub) // 10)]
+    t0 = time.perf_counter()
+    oracle.logcdf(inst.locs, inst.x, inst.m, c.family, c.nu, c.sigma2, c.range, c.nugget,
+                  inst.ordering, inst.qmc.n_points, inst.qmc.n_shifts, inst.qmc.seed,
+                  terms_subset=sub1, plan_cache=(perm, nbrs), processes=1)
+    t_one = time.perf_counter() - t0
     return {"value": inst.D / t_full, "unit": "terms/s", "cores": procs, "kind": "oracle",
             "sample": f"plan of all {inst.D} locations ({t_plan:.2f} s) + {len(sub)} of {inst.D} "
-                      f"terms ({t_terms:.2f} s on {procs} processes), extrapolated to all terms"}
+                      f"terms ({t_terms:.2f} s on {procs} processes), extrapolated to all terms",
+            "single_core": {"value": inst.D / (t_plan + t_one * inst.D / len(sub1)), "unit": "terms/s",
+                            "sample": f"the same plan + {len(sub1)} terms ({t_one:.2f} s) in one process"}}
 
 
 def autotune(V, n_points, n_shifts, ms, sp):
