@@ -20,6 +20,7 @@
 #include <thread>
 #include <unordered_map>
 
+#include "arena.h"
 #include "runtime.h"
 
 using namespace vecchia;
@@ -55,42 +56,6 @@ struct Slot {
   double* h_res = nullptr;       // pinned {log F, SE, bad term (as int64 bits)}
   InstDesc* h_stage = nullptr;   // pinned descriptor staging
   Request* req = nullptr;
-};
-
-// First-fit allocator over [0, size) in 256-byte units.
-struct Arena {
-  std::map<size_t, size_t> free;   // offset -> length
-  explicit Arena(size_t size) { free[0] = size; }
-  bool alloc(size_t n, size_t* off) {
-    n = (n + 255) / 256 * 256;
-    for (auto it = free.begin(); it != free.end(); ++it) {
-      if (it->second >= n) {
-        *off = it->first;
-        const size_t rest = it->second - n;
-        const size_t at = it->first + n;
-        free.erase(it);
-        if (rest) free[at] = rest;
-        return true;
-      }
-    }
-    return false;
-  }
-  void release(size_t off, size_t n) {
-    n = (n + 255) / 256 * 256;
-    auto it = free.emplace(off, n).first;
-    auto nx = std::next(it);
-    if (nx != free.end() && it->first + it->second == nx->first) {
-      it->second += nx->second;
-      free.erase(nx);
-    }
-    if (it != free.begin()) {
-      auto pv = std::prev(it);
-      if (pv->first + pv->second == it->first) {
-        pv->second += it->second;
-        free.erase(it);
-      }
-    }
-  }
 };
 
 }  // namespace

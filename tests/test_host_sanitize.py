@@ -1,7 +1,8 @@
-"""The host ordering code (the plan's step a0) built with AddressSanitizer and
-UndefinedBehaviorSanitizer by g++ and run on random, tied, duplicated and
-degenerate inputs; its permutations must equal the oracle's (brute-force
-definitions) and the sanitizers must stay silent. Host code only."""
+"""Host code built with AddressSanitizer and UndefinedBehaviorSanitizer by g++:
+the ordering code (the plan's step a0) on random, tied, duplicated and
+degenerate inputs, whose permutations must equal the oracle's (brute-force
+definitions), and the serving loop's first-fit arena against a brute-force
+model. The sanitizers must stay silent. Host code only."""
 import os
 import shutil
 import subprocess
@@ -60,3 +61,19 @@ def test_orderings_under_sanitizers(checker):
         coord, maxmin = _run(checker, locs)
         assert np.array_equal(coord, ordering.coord_order(locs))
         assert np.array_equal(maxmin, ordering.maxmin_order(locs))
+
+
+def test_serving_arena_against_a_brute_force_model(tmp_path):
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("g++ not available")
+    exe = str(tmp_path / "arena_check")
+    cmd = [gxx, "-std=c++17", "-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+           "-fno-sanitize-recover=undefined", "-I", CSRC,
+           os.path.join(ROOT, "tests", "host_sanitize", "arena_check.cpp"), "-o", exe]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        pytest.skip("sanitizer build unavailable: " + r.stderr[-300:])
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=1", UBSAN_OPTIONS="halt_on_error=1")
+    r = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=300)
+    assert r.returncode == 0 and r.stdout.strip() == "ok", (r.stdout[-500:], r.stderr[-2000:])
