@@ -223,3 +223,20 @@ def test_server_mix_of_plan_kinds_equals_standalone_calls():
     V.vecchia_server_destroy(srv)
     for p, _, _, _ in reqs:
         V.vecchia_plan_destroy(p)
+
+
+def test_saved_ordering_reproduces_the_plan():
+    # a plan is saved as its permutation (vecchia_plan_neighbours) and rebuilt
+    # with ORDER_GIVEN: same neighbours, same log-CDF bit for bit, no maxmin pass
+    torch = torch_cuda()
+    from paper_2007_15195_amd import vecchia as V
+    inst = W.small_random_instance(3000, 12, 81, n_points=512, n_shifts=3, precision=W.PREC_FP32)
+    a = V.vecchia_plan(inst.locs, W.ORDER_MAXMIN, inst.m, inst.cov)
+    perm, nbr = V.vecchia_plan_neighbours(a)
+    b = V.vecchia_plan(inst.locs, W.ORDER_GIVEN, inst.m, inst.cov, perm=perm)
+    perm2, nbr2 = V.vecchia_plan_neighbours(b)
+    assert np.array_equal(perm, perm2) and np.array_equal(nbr, nbr2)
+    ra, rb = _single(V, torch, a, inst), _single(V, torch, b, inst)
+    assert ra[0] == rb[0] and ra[1] == rb[1]
+    V.vecchia_plan_destroy(a)
+    V.vecchia_plan_destroy(b)
