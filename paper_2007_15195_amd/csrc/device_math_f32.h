@@ -8,8 +8,9 @@
 // fit_fp32_math.py (relative error < 1.4e-6 in FP32 for a in [0, 40]).
 //
 // Phi^{-1}: for q in (0, 1/2], z = -Phi^{-1}(q) is a (5,4) rational in
-// s = sqrt(-log2 q) (relative error < 3.1e-6 in FP32), where log2 q may carry
-// an exponent kept outside the FP32 number.
+// s = sqrt(-log2 q) (relative error < 3.1e-6 in FP32 for s <= 34); where
+// log2 q carries an exponent kept outside the FP32 number, a second rational
+// covers s in [34, 1100].
 //
 // Hardware v_log_f32 / v_exp_f32 (base 2), v_sqrt_f32 and v_rcp_f32 are used
 // directly; every argument they see is a normal FP32 number or zero.
@@ -35,6 +36,27 @@ __device__ __forceinline__ float ninv_tail_from_log2(float lq2) {
 #pragma unroll
   for (int c = 3; c >= 0; --c) q = fmaf(q, s, kZQ[c]);
   return p * fast_rcp(q);
+}
+
+// The split path's quantile: log2 q carries the exponent kept outside the FP32
+// number and reaches -2^20 - 126 (s up to 1025). Up to s = 34 the main rational
+// applies; beyond it a (3,2) rational fitted on s in [34, 1100] (relative error
+// < 3.3e-7 in FP32) replaces the main one's extrapolation.
+__device__ __forceinline__ float ninv_tail_from_log2_split(float lq2) {
+  const float s = fast_sqrt(-lq2);
+  float p = kZP[5];
+#pragma unroll
+  for (int c = 4; c >= 0; --c) p = fmaf(p, s, kZP[c]);
+  float q = kZQ[4];
+#pragma unroll
+  for (int c = 3; c >= 0; --c) q = fmaf(q, s, kZQ[c]);
+  float pw = kZPW[3];
+#pragma unroll
+  for (int c = 2; c >= 0; --c) pw = fmaf(pw, s, kZPW[c]);
+  float qw = kZQW[2];
+#pragma unroll
+  for (int c = 1; c >= 0; --c) qw = fmaf(qw, s, kZQW[c]);
+  return s > 34.0f ? pw * fast_rcp(qw) : p * fast_rcp(q);
 }
 
 // Phi(t) from v = kappa t, as e = em (exact unless em is split further by the

@@ -234,7 +234,7 @@ __device__ __forceinline__ void item_f32(const Item& it, const Aux32* __restrict
       const float lq = fast_log2(qt);
       float z = ninv_tail_from_log2(lq);
       if (__builtin_expect(split, 0)) {   // some lane's e carries 2^en
-        z = ninv_tail_from_log2(lq + en);
+        z = ninv_tail_from_log2_split(lq + en);
         en = 0.0f;
         split = false;
       }
@@ -360,7 +360,7 @@ __device__ __forceinline__ void item_f32_gen(const Item& it, const Aux32* __rest
       const float lq = fast_log2(qt);
       float z = ninv_tail_from_log2(lq);
       if (__builtin_expect(split, 0)) {
-        z = ninv_tail_from_log2(lq + en);
+        z = ninv_tail_from_log2_split(lq + en);
         en = 0.0f;
         split = false;
       }

@@ -40,8 +40,8 @@ __global__ __launch_bounds__(kProbeThreads) void probe_math(int what, int64_t n,
     o0 = ninv_tail_from_log2(fast_log2(q));
     o1 = q;
   } else if (what == VECCHIA_PROBE_NINV_LOG2_F32) {
-    // the same rational from log2 q = x directly (the split path's wide range)
-    o0 = ninv_tail_from_log2((float)x);
+    // the split path's quantile from log2 q = x directly (its exponents reach -2^20)
+    o0 = ninv_tail_from_log2_split((float)x);
   } else if (what == VECCHIA_PROBE_PHI_F64) {
     o0 = normcdf(x);
   } else {
