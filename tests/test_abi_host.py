@@ -83,29 +83,38 @@ def test_plan_rejects_bad_arguments_before_gpu_work():
         with pytest.raises(V.VecchiaError) as e:
             V.vecchia_plan(locs, W.ORDER_COORD, kwargs["m"], cov, stream=0)
         assert e.value.status == 1
-    with pytest.raises(V.VecchiaError):
+    with pytest.raises(V.VecchiaError) as e:
         V.vecchia_plan(np.random.default_rng(1).random((5, 3)), W.ORDER_COORD, 2, cov, stream=0)
-    with pytest.raises(V.VecchiaError):
+    assert e.value.status == 1
+    with pytest.raises(V.VecchiaError) as e:
         V.vecchia_plan(locs, W.ORDER_COORD, 2, V.make_cov(V.VECCHIA_COV_MATERN, 0.7, 1.0, 0.1), stream=0)
-    with pytest.raises(V.VecchiaError):
+    assert e.value.status == 1
+    with pytest.raises(V.VecchiaError) as e:
         V.vecchia_plan(locs, W.ORDER_COORD, 2, V.make_cov(V.VECCHIA_COV_MATERN, 1.5, -1.0, 0.1), stream=0)
-    with pytest.raises(V.VecchiaError):
+    assert e.value.status == 1
+    with pytest.raises(V.VecchiaError) as e:
         V.vecchia_plan_from_cov(np.array([[1.0, 0.5], [0.4, 1.0]]), 1, stream=0)   # not symmetric
-    with pytest.raises(V.VecchiaError):
+    assert e.value.status == 1
+    with pytest.raises(V.VecchiaError) as e:
         V.vecchia_plan_from_cov(np.eye(3), 2, nbr=[[], [0], [2]], stream=0)      # not preceding
+    assert e.value.status == 1
     obs = np.array([1, 0, 0, 1, 0], dtype=bool)
-    with pytest.raises(V.VecchiaError):
-        V.vecchia_plan_censored(locs, obs, W.ORDER_COORD, 32, cov, stream=0)
+    with pytest.raises(V.VecchiaError) as e:
+        V.vecchia_plan_censored(locs, obs, W.ORDER_COORD, 64, cov, stream=0)
+    assert e.value.status == 1
     with pytest.raises(ValueError):
         V.vecchia_plan_censored(locs, obs[:4], W.ORDER_COORD, 2, cov, stream=0)
     bad = np.array([1, 0, 2, 0, 0], dtype=np.uint8)
-    with pytest.raises(V.VecchiaError):
+    with pytest.raises(V.VecchiaError) as e:
         V._check(V.lib().vecchia_plan_censored(locs.ctypes.data, 5, 2, W.ORDER_COORD, None, bad.ctypes.data, 2,
                                                V.byref(cov), None, V.byref(V.c_void_p())))
-    with pytest.raises(V.VecchiaError):
+    assert e.value.status == 1
+    with pytest.raises(V.VecchiaError) as e:
         V.vecchia_plan_from_cov_censored(np.eye(3), 2, 4, stream=0)              # n_observed > D
-    with pytest.raises(V.VecchiaError):
+    assert e.value.status == 1
+    with pytest.raises(V.VecchiaError) as e:
         V.vecchia_plan_from_cov_censored(np.eye(3), 2, -1, stream=0)
+    assert e.value.status == 1
     with pytest.raises(V.VecchiaError) as e:
         V.vecchia_server_create(0, 4)
     assert e.value.status == 1
@@ -178,8 +187,9 @@ def test_mixture_arguments_rejected_on_the_host():
         with pytest.raises(V.VecchiaError) as e:
             V.vecchia_mixture_rule(mix, np.zeros(24))
         assert e.value.status == 1
-    with pytest.raises(V.VecchiaError):
+    with pytest.raises(V.VecchiaError) as e:
         V.vecchia_mixture_rule(V.make_mixture(0.0, 2.0, 8), np.full(24, np.nan))   # NaN search value
+    assert e.value.status == 1
 
 
 def test_censored_matrix_plan_host_setup_runs_before_device_work():
@@ -189,8 +199,9 @@ def test_censored_matrix_plan_host_setup_runs_before_device_work():
     import torch
     if torch.cuda.is_available():
         pytest.skip("a device is present: the GPU tests build these plans")
-    with pytest.raises(V.VecchiaError):
+    with pytest.raises(V.VecchiaError) as e:
         V.vecchia_plan_from_cov_censored(np.eye(4), 3, 2, nbr=[[], [0], [0, 1], [1, 2]], stream=0)
+    assert e.value.status == 4   # E_HIP: the host set-up passed, the device work could not start
 
 
 def test_mixture_batch_arguments_rejected_on_the_host():
@@ -199,14 +210,18 @@ def test_mixture_batch_arguments_rejected_on_the_host():
         V.vecchia_mixbatch_create([], 16, q)
     assert e.value.status == 1
     for n_nodes in (0, 65):
-        with pytest.raises(V.VecchiaError):
+        with pytest.raises(V.VecchiaError) as e:
             V.vecchia_mixbatch_create([None], n_nodes, q)
-    with pytest.raises(V.VecchiaError):
+        assert e.value.status == 1
+    with pytest.raises(V.VecchiaError) as e:
         V.vecchia_mixbatch_create([None], 16, V.make_qmc(0, 4, 1, V.VECCHIA_FP64))
-    with pytest.raises(V.VecchiaError):
+    assert e.value.status == 1
+    with pytest.raises(V.VecchiaError) as e:
         V.vecchia_mixbatch_create([None], 16, q)                                 # null plan
-    with pytest.raises(V.VecchiaError):
+    assert e.value.status == 1
+    with pytest.raises(V.VecchiaError) as e:
         V.vecchia_mixbatch_destroy(None)
+    assert e.value.status == 1
 
 
 
@@ -223,8 +238,9 @@ def test_anisotropic_map_gives_the_mahalanobis_distance():
                 want = C.mahalanobis_distance(pts[i], pts[j], phi, A)
                 got = float(np.hypot(*(mp[i] - mp[j])))
                 assert abs(got - want) <= 1e-13 * max(1.0, want)
-    with pytest.raises(V.VecchiaError):
+    with pytest.raises(V.VecchiaError) as e:
         V.vecchia_map_anisotropic(pts, 1.0, 0.0)
+    assert e.value.status == 1
 
 
 def test_oracle_anisotropic_coords_match_its_distance():
@@ -255,8 +271,9 @@ def test_block_plan_arguments_rejected_on_the_host():
         assert e.value.status == 1
     S = np.eye(4)
     for terms in ([([0, 1], 2)], [([0, 0], 1)], [([0, 5], 1)], [([], 0)], [(list(range(4)), -1)]):
-        with pytest.raises(V.VecchiaError):
+        with pytest.raises(V.VecchiaError) as e:
             V.vecchia_plan_from_cov_block(S, terms, stream=0)
+        assert e.value.status == 1
 
 
 def test_binding_constants_match_the_header():
