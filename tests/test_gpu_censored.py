@@ -203,7 +203,7 @@ def test_censored_mixture_matches_the_oracle(beta, gamma):
     np.testing.assert_allclose(nodes.cpu().numpy()[:, 0], ref["node_logF"], rtol=1e-9, atol=1e-9)
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32-independent"])
 def test_mixture_batch_rows_equal_single_mixtures(precision):
     # the censored log-likelihood over replicates in one batch: row t equals
     # vecchia_mixture_logcdf on replicate t's plan with seed + t, bit for bit, for
@@ -211,10 +211,11 @@ def test_mixture_batch_rows_equal_single_mixtures(precision):
     torch = torch_cuda()
     from paper_2007_15195_amd import vecchia as V
     prec = V.VECCHIA_FP64 if precision == "fp64" else V.VECCHIA_FP32_LOOP
+    indep = precision.endswith("independent")
     reps = [W.censored_replicate(200 + 60 * k, 8, 300 + k, frac_obs=0.04 + 0.05 * k) for k in range(5)]
     plans = [V.vecchia_plan_censored(r.inst.locs, r.observed, r.inst.ordering, r.inst.m, r.inst.cov)
              for r in reps]
-    q = V.make_qmc(1024, 4, 41, prec)
+    q = V.make_qmc(1024, 4, 41, prec, independent=indep)
     mb = V.vecchia_mixbatch_create(plans, 16, q)
     x = torch.tensor(np.concatenate([r.inst.x for r in reps]), dtype=torch.float64, device="cuda")
     for beta, gamma in ((0.82, 1.0), (0.3, 1.5)):
@@ -229,7 +230,7 @@ def test_mixture_batch_rows_equal_single_mixtures(precision):
         for t, (p, r) in enumerate(zip(plans, reps)):
             xs = torch.tensor(r.inst.x, dtype=torch.float64, device="cuda")
             one = torch.empty(2, dtype=torch.float64, device="cuda")
-            V.vecchia_mixture_logcdf(p, xs, mix, V.make_qmc(1024, 4, 41 + t, prec), one)
+            V.vecchia_mixture_logcdf(p, xs, mix, V.make_qmc(1024, 4, 41 + t, prec, independent=indep), one)
             torch.cuda.synchronize()
             assert np.array_equal(got[t], one.cpu().numpy()), (beta, t)
         assert abs(tot[0] - got[:, 0].sum()) <= 1e-12 * abs(tot[0])
