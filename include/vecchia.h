@@ -97,7 +97,8 @@ typedef struct {
   int32_t n_points;   /* N lattice points per shift, 1..VECCHIA_MAX_POINTS          */
   int32_t n_shifts;   /* R random shifts, 1..VECCHIA_MAX_SHIFTS (R = 1: SE is NaN)  */
   uint64_t seed;      /* keys the random shifts                                     */
-  int32_t precision;  /* VECCHIA_FP64 or VECCHIA_FP32_LOOP                          */
+  int32_t precision;  /* VECCHIA_FP64 or VECCHIA_FP32_LOOP (terms with a limit below -4
+                         standard deviations run in FP64 within an FP32 evaluation) */
   int32_t flags;      /* 0 or VECCHIA_QMC_INDEPENDENT                               */
 } vecchia_qmc;
 

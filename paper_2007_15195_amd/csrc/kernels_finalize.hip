@@ -70,7 +70,9 @@ __global__ __launch_bounds__(64 * kFinalizeWaves) void term_finalize(
       }
     }
     const double sn = wave_sum(pn), sd = wave_sum(pd), sc = wave_sum(pc);
-    if (I.precision == VECCHIA_FP32_LOOP && !indep && sc < sn)
+    // the log1p form needs the FP32 loop's complement sums (not kept by a promoted term's FP64 items)
+    const bool fp32_sums = I.precision == VECCHIA_FP32_LOOP && I.promote[t] == 0;
+    if (fp32_sums && !indep && sc < sn)
       lt = log1p(-sc / sd);
     else
       lt = log(sn) - log(sd);

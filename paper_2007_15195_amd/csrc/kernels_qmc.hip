@@ -177,6 +177,7 @@ template <int K, bool BLOCK>
 __device__ __forceinline__ void item_f32(const Item& it, const Aux32* __restrict__ aux32,
                                          const uint64_t* __restrict__ Zg, double* __restrict__ sums) {
   const InstDesc& I = *it.I;
+  if (uniform(I.promote[it.t]) != 0) return;   // this term runs in FP64 (qmc_promoted)
   const int lane = threadIdx.x & 63;
   const int sp = BLOCK ? uniform(I.split[it.i]) : K;   // denominator: the first sp factors
   const float* __restrict__ prep = reinterpret_cast<const float*>(I.prep) + it.i * I.prep_stride;
@@ -317,6 +318,7 @@ __device__ __forceinline__ void item_f32_gen(const Item& it, const Aux32* __rest
   __shared__ float ys[kMaxM][64];
   __shared__ uint64_t sh[kMaxM];
   const InstDesc& I = *it.I;
+  if (uniform(I.promote[it.t]) != 0) return;   // this term runs in FP64 (qmc_promoted)
   const int lane = threadIdx.x & 63;
   const int K = it.K;
   const bool block = I.split != nullptr;
@@ -430,8 +432,10 @@ __device__ __forceinline__ void item_f32_gen(const Item& it, const Aux32* __rest
   }
 }
 
+// prep: the term's FP64 rows (the instance's own, or a promoted term's slot)
 __device__ __forceinline__ void item_f64_gen(const Item& it, const Aux64* __restrict__ aux64,
-                                             const uint64_t* __restrict__ Zg, double* __restrict__ sums) {
+                                             const uint64_t* __restrict__ Zg, double* __restrict__ sums,
+                                             const double* __restrict__ prep) {
   __shared__ double srow[kGenRowElems];
   __shared__ double ys[kMaxM][64];
   __shared__ uint64_t sh[kMaxM];
@@ -440,7 +444,6 @@ __device__ __forceinline__ void item_f64_gen(const Item& it, const Aux64* __rest
   const int K = it.K;
   const bool block = I.split != nullptr;
   const int sp = block ? uniform(I.split[it.i]) : K;
-  const double* __restrict__ prep = reinterpret_cast<const double*>(I.prep) + it.i * I.prep_stride;
   const double e0 = aux64[it.t].e0;
   const int p_begin = 1 + it.c * I.chunk_points;
   const int p_last = min(I.n_points, p_begin + I.chunk_points - 1);
@@ -501,7 +504,55 @@ __global__ __launch_bounds__(64) void qmc_gen_f64(const InstDesc* __restrict__ i
                                                   const Aux64* __restrict__ aux64, const uint64_t* __restrict__ Zg,
                                                   double* __restrict__ sums, int64_t item_base) {
   const Item it = decode_item(insts, ranges, n_ranges, item_base + (int64_t)blockIdx.x);
-  item_f64_gen(it, aux64, Zg, sums);
+  item_f64_gen(it, aux64, Zg, sums, reinterpret_cast<const double*>(it.I->prep) + it.i * it.I->prep_stride);
+}
+
+__device__ __forceinline__ int find_inst_q(const int64_t* __restrict__ bases, int n, int64_t t) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (bases[mid] <= t) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Promoted terms of FP32 instances, in FP64: each wave takes the next
+// (list entry, item) pair from the work counter until the count x ipt_max pairs
+// are used up; pairs past a term's own item count are skipped. Every wave
+// leaves once the counter passes the end, so the grid always drains.
+__global__ __launch_bounds__(64) void qmc_promoted(const InstDesc* __restrict__ insts, int n_inst,
+                                                   const int64_t* __restrict__ term_bases,
+                                                   const Aux64* __restrict__ aux64, const uint64_t* __restrict__ Zg,
+                                                   double* __restrict__ sums, const int32_t* __restrict__ plist,
+                                                   int64_t* __restrict__ pctr, int plist_cap, int ipt_max) {
+  const int lane = threadIdx.x;
+  const int64_t count = min(pctr[0], (int64_t)plist_cap);
+  const int64_t total = count * (int64_t)ipt_max;
+  for (;;) {
+    unsigned long long got = 0;
+    if (lane == 0) got = atomicAdd(reinterpret_cast<unsigned long long*>(&pctr[1]), 1ULL);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)got);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(got >> 32));
+    const int64_t v = (int64_t)(((uint64_t)hi << 32) | lo);
+    if (v >= total) break;
+    const int64_t e = v / ipt_max;
+    const int j = (int)(v - e * ipt_max);
+    const int64_t t = uniform(plist[e]);
+    const int ii = uniform(find_inst_q(term_bases, n_inst, t));
+    const InstDesc& I = insts[ii];
+    const int ns = uniform(I.n_shifts), nc = uniform(I.n_chunks);
+    if (j >= uniform(I.passes) * ns * nc) continue;
+    Item it;
+    it.I = &I;
+    it.i = t - term_bases[ii];
+    it.t = t;
+    it.r = j / nc;
+    it.c = j - it.r * nc;
+    it.second = it.r >= ns;
+    it.sr = it.second ? it.r - ns : it.r;
+    it.K = uniform(I.sovk[it.i]);
+    item_f64_gen(it, aux64, Zg, sums, I.prep64 + e * I.prep64_stride);
+  }
 }
 
 hipError_t qmc_gen_dispatch(int precision, const InstDesc* insts, const RangeDesc* ranges, int n_ranges,
@@ -590,6 +641,17 @@ hipError_t qmc_switch_f32_long(int K, const InstDesc* insts, const RangeDesc* ra
 }
 
 }  // namespace
+
+hipError_t launch_qmc_promoted(const InstDesc* d_insts, int n_inst, const int64_t* d_term_bases, const Aux64* aux64,
+                               const uint64_t* d_Z, double* sums, const int32_t* plist, int64_t* pctr,
+                               int plist_cap, int ipt_max, hipStream_t s) {
+  if (plist_cap <= 0 || ipt_max <= 0) return hipSuccess;
+  const int64_t pairs = (int64_t)plist_cap * ipt_max;
+  const unsigned grid = (unsigned)(pairs < 2048 ? pairs : 2048);
+  hipLaunchKernelGGL(qmc_promoted, dim3(grid), dim3(64), 0, s, d_insts, n_inst, d_term_bases, aux64, d_Z, sums,
+                     plist, pctr, plist_cap, ipt_max);
+  return hipGetLastError();
+}
 
 hipError_t launch_qmc(int K, int precision, bool block, const InstDesc* d_insts, const RangeDesc* d_ranges,
                       int n_ranges, int64_t n_items, const Aux64* aux64, const Aux32* aux32,

@@ -54,7 +54,8 @@ __global__ __launch_bounds__(64) void term_setup(const InstDesc* __restrict__ in
                                                  Aux64* __restrict__ aux64,
                                                  Aux32* __restrict__ aux32, int64_t term_base) {
   __shared__ double C[kMaxVars][kMaxVars + 1];
-  __shared__ double px[kMaxVars], py[kMaxVars], pb[kMaxVars], pw[kMaxVars];
+  __shared__ double px[kMaxVars], py[kMaxVars], pb[kMaxVars], pw[kMaxVars], cdiag[kMaxVars];
+  __shared__ long long pslot;
   __shared__ int pv[kMaxVars];
   __shared__ double piv;
   const int lane = threadIdx.x;
@@ -102,8 +103,14 @@ __global__ __launch_bounds__(64) void term_setup(const InstDesc* __restrict__ in
       if (a == c) cv += I.nugget;
     }
     C[a][c] = cv;
+    if (a == c) cdiag[a] = cv;
   }
   __syncthreads();
+  // FP32 instances: a variable of the chain whose limit lies below kPromoteZ
+  // standard deviations sends the term to the FP64 kernel (deep lower tails
+  // are where the FP32 loop's rounding of the scaled limits shows)
+  const bool deep_var = lane < n && !eq && lane <= k && bl < kPromoteZ * sqrt(cdiag[slot]);
+  const bool want_promote = I.precision == VECCHIA_FP32_LOOP && __ballot(deep_var) != 0;
   bool bad = false;
   for (int j = 0; j < n; ++j) {
     double s = 0.0;
@@ -139,6 +146,24 @@ __global__ __launch_bounds__(64) void term_setup(const InstDesc* __restrict__ in
   const double nan = __builtin_nan("");
   const bool f32 = I.precision == VECCHIA_FP32_LOOP;
   const bool density = i < I.n_obs;
+  // a promoted term takes a slot of the batch's list (none left: it stays FP32)
+  bool promoted = false;
+  if (want_promote && !density && !bad && !zero && n - q >= 2) {
+    if (lane == 0) pslot = (long long)atomicAdd(reinterpret_cast<unsigned long long*>(I.pctr), 1ULL);
+    __syncthreads();
+    promoted = pslot < I.plist_cap;
+  }
+  if (promoted && lane >= q && lane < n) {
+    const int a = lane - q;
+    const double laa = C[lane][lane];
+    double* row = I.prep64 + pslot * (int64_t)I.prep64_stride + (int64_t)a * (a + 1) / 2;
+    for (int c = 0; c < a; ++c) row[c] = C[lane][q + c] / laa;
+    row[a] = bs / laa;
+  }
+  if (f32 && lane == 0) {
+    I.promote[t] = promoted ? 1 : 0;
+    if (promoted) I.plist[pslot] = (int32_t)t;
+  }
   if (!density && lane >= q && lane < n) {
     const int a = lane - q;   // row of the conditional block
     const double laa = C[lane][lane];

@@ -264,6 +264,8 @@ vecchia_status Batch::create(const std::vector<vecchia_plan_s*>& plans,
     const int prec = qmcs[j].precision;
     const int nv = P->block > 0 ? P->block_nv : P->m + 1;   // variables per term, at most
     const int stride = (int)align_up((size_t)nv * (nv + 1) / 2, prec == VECCHIA_FP32_LOOP ? 4 : 2);
+    if (prec == VECCHIA_FP32_LOOP)
+      b->prep64_stride_ = std::max(b->prep64_stride_, (int)align_up((size_t)nv * (nv + 1) / 2, 2));
     InstDesc& d = b->desc_[j];
     std::memset(&d, 0, sizeof(d));
     d.xs = P->d_xs;
@@ -367,6 +369,14 @@ vecchia_status Batch::create(const std::vector<vecchia_plan_s*>& plans,
   take(sizeof(double2) * tb);
   take(sizeof(int64_t) * n);
   take(prep);
+  if (b->any_f32_) {
+    // promoted terms (FP32 instances): flags, list, counters and a bounded FP64 row buffer
+    b->plist_cap_ = (int32_t)std::min<int64_t>(tb, std::max<int64_t>(256, tb / 8));
+    take(sizeof(int32_t) * tb);
+    take(sizeof(int32_t) * b->plist_cap_);
+    take(sizeof(int64_t) * 2);
+    take(sizeof(double) * (size_t)b->plist_cap_ * b->prep64_stride_);
+  }
   b->ws_bytes_ = off;
   *out = std::move(b);
   return VECCHIA_OK;
@@ -402,9 +412,23 @@ vecchia_status Batch::allocate() {
   d_term_res_ = reinterpret_cast<double2*>(take(sizeof(double2) * total_terms_));
   d_bad_ = reinterpret_cast<int64_t*>(take(sizeof(int64_t) * n));
   d_prep_ = take(prep_bytes_);
+  if (any_f32_) {
+    d_promote_ = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * total_terms_));
+    d_plist_ = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * plist_cap_));
+    d_pctr_ = reinterpret_cast<int64_t*>(take(sizeof(int64_t) * 2));
+    d_prep64_ = reinterpret_cast<double*>(take(sizeof(double) * (size_t)plist_cap_ * prep64_stride_));
+  }
   for (int j = 0; j < n; ++j) {
     desc_[j].prep = d_prep_ + prep_off_[j];
     desc_[j].bad_term = d_bad_ + j;
+    const bool f32 = desc_[j].precision == VECCHIA_FP32_LOOP;
+    desc_[j].promote = f32 ? d_promote_ : nullptr;
+    desc_[j].plist = f32 ? d_plist_ : nullptr;
+    desc_[j].pctr = f32 ? d_pctr_ : nullptr;
+    desc_[j].prep64 = f32 ? d_prep64_ : nullptr;
+    desc_[j].prep64_stride = prep64_stride_;
+    desc_[j].plist_cap = plist_cap_;
+    if (f32) ipt_max_ = std::max(ipt_max_, desc_[j].passes * desc_[j].n_shifts * desc_[j].n_chunks);
   }
   if (!ext_stage_) {
     e = hipHostMalloc(reinterpret_cast<void**>(&h_stage_), sizeof(InstDesc) * n * kRing, hipHostMallocDefault);
@@ -433,6 +457,7 @@ vecchia_status Batch::enqueue(hipStream_t s) {
   const int n = (int)plans_.size();
   const bool prof = profiling_enabled();
   hipError_t e = launch_fill_i64(d_bad_, n, INT64_MAX, s);
+  if (e == hipSuccess && any_f32_) e = launch_fill_i64(d_pctr_, 2, 0, s);
   if (e == hipSuccess)
     e = launch_setup(d_desc_, n, d_term_bases_, total_terms_, d_aux64_, d_aux32_, s);
   // fork: side streams start after the setup kernel
@@ -462,6 +487,11 @@ vecchia_status Batch::enqueue(hipStream_t s) {
     e = hipEventRecord(join_ev_[k], side_[k]);
     if (e == hipSuccess) e = hipStreamWaitEvent(s, join_ev_[k], 0);
   }
+  // the FP32 instances' promoted terms, in FP64 (a short persistent grid that
+  // finds nothing to do when no term was promoted)
+  if (e == hipSuccess && any_f32_ && ipt_max_ > 0)
+    e = launch_qmc_promoted(d_desc_, n, d_term_bases_, d_aux64_, d_Z_, d_sums_, d_plist_, d_pctr_, plist_cap_,
+                            ipt_max_, s);
   if (e == hipSuccess)
     e = launch_finalize(d_desc_, n, d_term_bases_, total_terms_, d_aux64_, d_sums_, d_term_res_, s);
   if (e != hipSuccess) return hip_error(e, "kernel launch");

@@ -107,6 +107,14 @@ class Batch {
   int64_t* d_bad_ = nullptr;
   char* d_prep_ = nullptr;
   const uint64_t* d_Z_ = nullptr;
+  // promoted terms of FP32 instances (see InstDesc)
+  int32_t* d_promote_ = nullptr;
+  int32_t* d_plist_ = nullptr;
+  int64_t* d_pctr_ = nullptr;
+  double* d_prep64_ = nullptr;
+  int32_t prep64_stride_ = 0;
+  int32_t plist_cap_ = 0;
+  int32_t ipt_max_ = 0;
 
   static constexpr int kRing = 4;       // pinned descriptor staging slots
   InstDesc* h_stage_ = nullptr;

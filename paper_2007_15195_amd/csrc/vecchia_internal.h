@@ -10,6 +10,7 @@ namespace vecchia {
 
 constexpr int kMaxM = VECCHIA_MAX_M;   // conditioning-set size limit
 constexpr int kMaxVars = kMaxM + 1;    // variables per term
+constexpr double kPromoteZ = -4.0;     // FP32 instances: terms with a limit below this many SDs run in FP64
 // Chains of up to this many steps run fully unrolled with y in registers;
 // longer ones (up to kMaxM) run in the general kernel with y in LDS.
 constexpr int kMaxUnrolledK = 31;
@@ -31,6 +32,17 @@ struct InstDesc {
   double* out;             // {log F, SE}
   double* terms_out;       // D x 2 user order, or null
   void* prep;              // per-term scaled Cholesky rows (double or float), term 0
+  // FP32 instances: terms with a limit below kPromoteZ standard deviations are
+  // evaluated in FP64 instead (the FP32 items of such a term exit at once).
+  // promote[t] (global term index) is 1 for them; their FP64 rows sit at
+  // prep64 + slot * prep64_stride, slot = their position in plist (at most
+  // plist_cap); pctr = {promoted count, work counter}. Shared by the batch.
+  int32_t* promote;
+  double* prep64;
+  int32_t* plist;
+  int64_t* pctr;
+  int32_t prep64_stride;
+  int32_t plist_cap;
   int64_t D;
   int64_t n_terms;         // terms: D, or the number of groups of a block plan
   // block plans (joint terms, Section 3.2): term i's variables are
@@ -103,6 +115,12 @@ hipError_t launch_setup(const InstDesc* d_insts, int n_inst, const int64_t* d_te
 hipError_t launch_qmc(int K, int precision, bool block, const InstDesc* d_insts, const RangeDesc* d_ranges,
                       int n_ranges, int64_t n_items, const Aux64* aux64, const Aux32* aux32,
                       const uint64_t* d_Z, double* sums, hipStream_t s);
+// The promoted terms of FP32 instances in FP64: a persistent grid takes
+// (term, item) pairs from the device-side list (pctr[0] entries, at most
+// plist_cap; ipt_max items per term at most) until none is left.
+hipError_t launch_qmc_promoted(const InstDesc* d_insts, int n_inst, const int64_t* d_term_bases, const Aux64* aux64,
+                               const uint64_t* d_Z, double* sums, const int32_t* plist, int64_t* pctr,
+                               int plist_cap, int ipt_max, hipStream_t s);
 // Scale-mixture quadrature weights (log), passed by value to the combine kernel.
 constexpr int kMaxMixNodes = 64;
 constexpr int kMixSearch = VECCHIA_MIX_SEARCH_NODES;

@@ -275,10 +275,11 @@ def test_fp32_general_kernel_against_fp64():
 
 @pytest.mark.parametrize("case", [(210, 169, 8, 2049, 7, 1.5, W.ORDER_COORD, 0.7, -2.0),
                                   (92, 195, 6, 1000, 3, 1.5, W.ORDER_MAXMIN, 0.7, -2.0)])
-def test_fp32_in_the_deep_lower_tail_stays_within_a_tenth_of_the_se(case):
-    # thresholds near -2.9 sigma on average: a few terms have limits below -4.4 sigma
-    # and heavy-tailed estimates (SE above 0.5); there FP32 rounding moves a term by
-    # up to 10% of its SE (beyond 1e-3), while the total stays within 1e-3 relative
+def test_fp32_in_the_deep_lower_tail_meets_the_per_term_bar(case):
+    # thresholds near -2.9 sigma on average: the terms with a limit below -4 sigma
+    # (where FP32 rounding of the scaled limits moved heavy-tailed estimates by up
+    # to 0.07) are promoted to FP64 inside the FP32 evaluation; every term then
+    # meets the 1e-3 bar and the promoted ones equal the FP64 mode's value
     k, D, m, N, R, nu, order, scale, mean_x = case
     res = {}
     for prec in (W.PREC_FP64, W.PREC_FP32):
@@ -287,6 +288,12 @@ def test_fp32_in_the_deep_lower_tail_stays_within_a_tenth_of_the_se(case):
         res[prec] = gpu_run(inst)
     t64, t32 = res[W.PREC_FP64]["terms"], res[W.PREC_FP32]["terms"]
     d = np.abs(t32[:, 0] - t64[:, 0])
-    assert np.all(d <= np.maximum(1e-3, 0.1 * t64[:, 1])), (d.max(), t64[np.argmax(d)])
+    assert d.max() <= 1e-3, (d.max(), t64[np.argmax(d)])
+    # the promoted terms (a limit below -4 sd; unit variance here up to the nugget)
+    x = inst.x / scale
+    perm, nbr = res[W.PREC_FP32]["perm"], res[W.PREC_FP32]["nbr"]
+    deep = [perm[i] for i in range(D) if np.min(x[perm[[*nbr[i][nbr[i] >= 0], i]]]) < -4.0 and min(i, m) >= 1]
+    assert len(deep) > 0
+    assert np.max(np.abs(t32[deep, 0] - t64[deep, 0])) <= 1e-10
     tot64, tot32 = res[W.PREC_FP64]["out"][0], res[W.PREC_FP32]["out"][0]
     assert abs(tot32 - tot64) <= 1e-3 * abs(tot64)
