@@ -75,7 +75,7 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="uniform2500_matern15_m10",
                     choices=["uniform2500_matern15_m10", "grid400_exp_m5"])
     ap.add_argument("--fp64-steps", type=int, default=3)
