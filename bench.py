@@ -68,7 +68,7 @@ VALU_PEAK_TSLOTS = 256 * 2.4e9 * 128 / 1e12
 TRANS_PER_STEP = {"exp": 1, "log": 1, "rcp": 2, "sqrt": 1}
 # HBM bytes per launch of qmc_f32<10> from rocprofv3 FETCH_SIZE x 2.0 +
 # WRITE_SIZE x 1.0 (factors from a 256 MiB copy); None once the kernel changes.
-TRAFFIC_BYTES_F32_K10 = 12.19e6
+TRAFFIC_BYTES_F32_K10 = 12.28e6    # (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000) per launch, profiles/qmc_f32_k10_uniform2500_pmc.md
 
 
 def parse():

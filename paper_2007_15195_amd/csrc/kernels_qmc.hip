@@ -527,6 +527,7 @@ __global__ __launch_bounds__(64) void qmc_promoted(const InstDesc* __restrict__ 
                                                    int64_t* __restrict__ pctr, int plist_cap, int ipt_max) {
   const int lane = threadIdx.x;
   const int64_t count = min(pctr[0], (int64_t)plist_cap);
+  if (count == 0) return;   // nothing promoted: no wave touches the work counter
   const int64_t total = count * (int64_t)ipt_max;
   for (;;) {
     unsigned long long got = 0;
