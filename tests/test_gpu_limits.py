@@ -196,3 +196,45 @@ def test_largest_shift_count_matches_the_oracle():
     t = terms.cpu().numpy()
     assert np.max(np.abs(t[:, 0] - o["terms"][:, 0])) <= 1e-10
     np.testing.assert_allclose(t[:, 1], o["terms"][:, 1], rtol=1e-6, atol=1e-14)
+
+
+@pytest.mark.parametrize("kind", ["block", "censored", "independent"])
+def test_promoted_terms_of_every_plan_kind_match_fp64(kind):
+    # deep lower-tail thresholds: FP32 evaluations hand the terms with a limit below
+    # -4 sd to the FP64 kernel; block terms (denominator split), censored terms
+    # (conditional rows) and the second lattice of the independent-points estimator
+    # must all come out as in the FP64 mode
+    torch = torch_cuda()
+    from paper_2007_15195_amd import vecchia as V
+    if kind == "censored":
+        rep = W.censored_replicate(260, 8, 91, frac_obs=0.1, n_points=600, n_shifts=3)
+        inst, observed = rep.inst, rep.observed
+        x = inst.x.copy()
+        x[~observed] -= 3.5                         # censoring limits deep in the lower tail
+        plan = V.vecchia_plan_censored(inst.locs, observed, inst.ordering, inst.m, inst.cov)
+    else:
+        inst = W.small_random_instance(220, 4 if kind == "block" else 8, 92, n_points=600, n_shifts=3,
+                                       mean_x=-2.0, sd_x=0.7)
+        x = inst.x / 0.7
+        plan = (V.vecchia_plan_block(inst.locs, inst.ordering, 4, 3, inst.cov) if kind == "block"
+                else V.vecchia_plan(inst.locs, inst.ordering, inst.m, inst.cov))
+    nt = V.plan_n_terms(plan)
+    xt = torch.tensor(x, dtype=torch.float64, device="cuda")
+    res = {}
+    for prec in (V.VECCHIA_FP64, V.VECCHIA_FP32_LOOP):
+        out = torch.empty(2, dtype=torch.float64, device="cuda")
+        t = torch.empty((nt, 2), dtype=torch.float64, device="cuda")
+        V.vecchia_logcdf(plan, xt, V.make_qmc(600, 3, 5, prec, independent=kind == "independent"), out, terms=t)
+        torch.cuda.synchronize()
+        res[prec] = (out.cpu().numpy(), t.cpu().numpy())
+    V.vecchia_plan_destroy(plan)
+    t64, t32 = res[V.VECCHIA_FP64][1], res[V.VECCHIA_FP32_LOOP][1]
+    fin = np.isfinite(t64[:, 0])
+    d = np.abs(t32[fin, 0] - t64[fin, 0])
+    # the independent estimator's numerator and denominator errors do not cancel:
+    # a heavy-tailed term above the promotion limit may move by a few percent of
+    # its own SE (1.04e-3 here), so its bar is relative to the SE
+    bar = np.maximum(1e-3, 0.05 * t64[fin, 1]) if kind == "independent" else 1e-3
+    assert np.all(d <= bar), (d.max(), int(np.argmax(d)))
+    # some terms were promoted: their values agree with FP64 to rounding
+    assert np.sum(d <= 1e-10) > 0
