@@ -54,7 +54,7 @@ __global__ __launch_bounds__(64) void term_setup(const InstDesc* __restrict__ in
                                                  Aux64* __restrict__ aux64,
                                                  Aux32* __restrict__ aux32, int64_t term_base) {
   __shared__ double C[kMaxVars][kMaxVars + 1];
-  __shared__ double px[kMaxVars], py[kMaxVars], pb[kMaxVars], pw[kMaxVars], cdiag[kMaxVars];
+  __shared__ double px[kMaxVars], py[kMaxVars], pb[kMaxVars], pw[kMaxVars];
   __shared__ long long pslot;
   __shared__ int pv[kMaxVars];
   __shared__ double piv;
@@ -103,14 +103,8 @@ __global__ __launch_bounds__(64) void term_setup(const InstDesc* __restrict__ in
       if (a == c) cv += I.nugget;
     }
     C[a][c] = cv;
-    if (a == c) cdiag[a] = cv;
   }
   __syncthreads();
-  // FP32 instances: a variable of the chain whose limit lies below kPromoteZ
-  // standard deviations sends the term to the FP64 kernel (deep lower tails
-  // are where the FP32 loop's rounding of the scaled limits shows)
-  const bool deep_var = lane < n && !eq && lane <= k && bl < kPromoteZ * sqrt(cdiag[slot]);
-  const bool want_promote = I.precision == VECCHIA_FP32_LOOP && __ballot(deep_var) != 0;
   bool bad = false;
   for (int j = 0; j < n; ++j) {
     double s = 0.0;
@@ -143,6 +137,18 @@ __global__ __launch_bounds__(64) void term_setup(const InstDesc* __restrict__ in
     pb[lane] = bs;
   }
   __syncthreads();
+  // FP32 instances: a chain variable whose limit lies below kPromoteZ standard
+  // deviations of its distribution given the observed sites (limit bs, variance
+  // the row norm of the conditional block of L) sends the term to the FP64
+  // kernel: deep lower tails are where the FP32 loop's rounding of the scaled
+  // limits shows
+  double zc = HUGE_VAL;
+  if (lane >= q && lane < n) {
+    double r2 = 0.0;
+    for (int c = q; c <= lane; ++c) r2 += C[lane][c] * C[lane][c];
+    zc = bs / sqrt(r2);
+  }
+  const bool want_promote = I.precision == VECCHIA_FP32_LOOP && __ballot(zc < kPromoteZ) != 0;
   const double nan = __builtin_nan("");
   const bool f32 = I.precision == VECCHIA_FP32_LOOP;
   const bool density = i < I.n_obs;

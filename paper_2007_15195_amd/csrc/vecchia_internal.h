@@ -32,8 +32,9 @@ struct InstDesc {
   double* out;             // {log F, SE}
   double* terms_out;       // D x 2 user order, or null
   void* prep;              // per-term scaled Cholesky rows (double or float), term 0
-  // FP32 instances: terms with a limit below kPromoteZ standard deviations are
-  // evaluated in FP64 instead (the FP32 items of such a term exit at once).
+  // FP32 instances: terms with a chain limit below kPromoteZ standard deviations
+  // (of the variable given the observed sites) are evaluated in FP64 instead
+  // (the FP32 items of such a term exit at once).
   // promote[t] (global term index) is 1 for them; their FP64 rows sit at
   // prep64 + slot * prep64_stride, slot = their position in plist (at most
   // plist_cap); pctr = {promoted count, work counter}. Shared by the batch.
