@@ -105,3 +105,25 @@ def test_full_rejects_fp32_and_censored_plans():
     with pytest.raises(V.VecchiaError):
         V.vecchia_full_logcdf(cplan, x, V.make_qmc(64, 2, 1, V.VECCHIA_FP64), out)
     V.vecchia_plan_destroy(cplan)
+
+
+def test_full_with_infinite_thresholds():
+    # +inf: the component is unconstrained (the estimator matches the oracle's to
+    # 1e-10); -inf anywhere: log F = -inf
+    torch = torch_cuda()
+    from paper_2007_15195_amd import vecchia as V
+    inst = W.small_random_instance(40, 5, 541, ordering=W.ORDER_MAXMIN, n_points=300, n_shifts=4)
+    x = inst.x.copy()
+    x[[3, 17, 30]] = np.inf
+    plan = V.vecchia_plan(inst.locs, inst.ordering, inst.m, inst.cov)
+    q = V.make_qmc(300, 4, 9, V.VECCHIA_FP64)
+    got = _full(V, torch, plan, x, q)
+    perm, _ = V.vecchia_plan_neighbours(plan)
+    c = inst.cov
+    S = covariance.cov_matrix(inst.locs[perm], c.family, c.nu, c.sigma2, c.range, c.nugget)
+    lf, se, _ = FS.logcdf_full(S, x[perm], 300, 4, 9)
+    assert abs(got[0] - lf) <= 1e-10 * max(1.0, abs(lf))
+    x[11] = -np.inf
+    got = _full(V, torch, plan, x, q)
+    assert got[0] == -math.inf
+    V.vecchia_plan_destroy(plan)
