@@ -35,7 +35,7 @@ namespace vecchia {
 namespace {
 
 constexpr int kCholB = 32;     // Cholesky block
-constexpr int kSovB = 16;      // SOV dimension block (registers)
+constexpr int kSovB = 32;      // SOV dimension block (registers)
 constexpr int kSovThreads = 256;
 
 struct CovArgs {
@@ -166,7 +166,9 @@ __device__ __forceinline__ double log_ncdf(double t) {
                  : log1p(-0.5 * erfc(t * 0.70710678118654752440));
 }
 
-__device__ __noinline__ double ncdf_full(double t) { return normcdf(t); }
+// The FP64 quantile stays out of line: inlined, it takes full_sov to the full
+// register file with spills.
+__device__ __forceinline__ double ncdf_full(double t) { return normcdf(t); }
 __device__ __noinline__ double ncdfinv_full(double u) { return normcdfinv(u); }
 
 // L: D x D with L in the lower triangle and L^T in the upper; b: D limits;
@@ -182,7 +184,7 @@ struct SovSizes {
 __global__ __launch_bounds__(kSovThreads) void full_sov(const double* __restrict__ L, const double* __restrict__ bl,
                                                         const uint64_t* __restrict__ Zt, double* __restrict__ Y,
                                                         double2* __restrict__ part, SovSizes a) {
-  __shared__ double Ld[kSovB][kSovB + 1];       // the block's own rows
+  __shared__ double Ld[2 * kSovB][kSovB + 1];   // the block's own rows, then zeros
   __shared__ double red_m[kSovThreads / 64], red_s[kSovThreads / 64];
   const int r = blockIdx.y;
   const int64_t p = (int64_t)blockIdx.x * kSovThreads + threadIdx.x;   // point p + 1
@@ -197,44 +199,45 @@ __global__ __launch_bounds__(kSovThreads) void full_sov(const double* __restrict
     for (int q = 0; q < kSovB; ++q) acc[q] = q < nb ? bl[j0 + q] : 0.0;
     // earlier dimensions: acc_q -= sum_{c < j0} L[j0 + q][c] y_c, the column
     // L[j0.., c] being row c of the mirrored upper triangle (c < j0 <= j0 + q).
-    // All kSovB entries are read (one wide scalar load); in a last, ragged block
+    // All kSovB entries are read (wide scalar loads); in a last, ragged block
     // the ones past the row end fall in row c + 1 or in the limits that follow A
     // in the workspace, and only feed acc entries that are never used.
     const double* __restrict__ Lu = L + j0;
-#pragma unroll 4
+#pragma unroll 2
     for (int64_t c = 0; c < j0; ++c) {
       const double yc = Y[c * a.S + s];
       const double* __restrict__ col = Lu + c * D;
 #pragma unroll
       for (int q = 0; q < kSovB; ++q) acc[q] -= col[q] * yc;
     }
+    // the block's own rows, zero past its end, so that row q + 1 + i below is
+    // always in the array
     __syncthreads();
-    for (int idx = threadIdx.x; idx < kSovB * kSovB; idx += kSovThreads) {
+    for (int idx = threadIdx.x; idx < 2 * kSovB * kSovB; idx += kSovThreads) {
       const int q = idx / kSovB, c = idx - q * kSovB;
       Ld[q][c] = (q < nb && c <= q) ? L[(j0 + q) * D + j0 + c] : 0.0;
     }
     __syncthreads();
-    double yb[kSovB];
-#pragma unroll
-    for (int q = 0; q < kSovB; ++q) {
-      yb[q] = 0.0;
-      if (q < nb) {
-        double v = acc[q];
-#pragma unroll
-        for (int c = 0; c < q; ++c) v -= Ld[q][c] * yb[c];
-        const double t = v / Ld[q][q];
-        e = ncdf_full(t);
-        lp += log_ncdf(t);
-        const int64_t dim = j0 + q;
-        if (dim < D - 1) {
-          const uint64_t S = splitmix64(a.seed, (1ULL << 63) | ((uint64_t)r << 32) | (uint64_t)dim);
-          const uint64_t U = (uint64_t)(p + 1) * Zt[dim] + S;
-          const double w = lattice_coord_f64(U);
-          const double y = ncdfinv_full(fmax(w * e, 2.2250738585072014e-308));
-          yb[q] = y;
-          if (live) Y[dim * a.S + s] = y;
-        }
+    // The recursion inside the block, right-looking: acc[0] always holds the
+    // current dimension's (b - sum L y); once its y is drawn, the later entries
+    // take their term in it and move down one place. The loop is not unrolled,
+    // so the Phi and Phi^-1 code is inlined once and acc stays in registers.
+#pragma unroll 1
+    for (int q = 0; q < nb; ++q) {
+      const double t = acc[0] / Ld[q][q];
+      e = ncdf_full(t);
+      lp += log_ncdf(t);
+      const int64_t dim = j0 + q;
+      double y = 0.0;
+      if (dim < D - 1) {
+        const uint64_t S = splitmix64(a.seed, (1ULL << 63) | ((uint64_t)r << 32) | (uint64_t)dim);
+        const uint64_t U = (uint64_t)(p + 1) * Zt[dim] + S;
+        const double w = lattice_coord_f64(U);
+        y = ncdfinv_full(fmax(w * e, 2.2250738585072014e-308));
+        if (live) Y[dim * a.S + s] = y;
       }
+#pragma unroll
+      for (int i = 0; i + 1 < kSovB; ++i) acc[i] = acc[i + 1] - Ld[q + 1 + i][q] * y;
     }
   }
   // workgroup {max, sum exp(lp - max)} over its live points
