@@ -205,7 +205,8 @@ __global__ __launch_bounds__(kSovThreads) void full_sov(const double* __restrict
     const double* __restrict__ Lu = L + j0;
 #pragma unroll 2
     for (int64_t c = 0; c < j0; ++c) {
-      const double yc = Y[c * a.S + s];
+      // streamed past the caches: each y is read once per block
+      const double yc = __builtin_nontemporal_load(&Y[c * a.S + s]);
       const double* __restrict__ col = Lu + c * D;
 #pragma unroll
       for (int q = 0; q < kSovB; ++q) acc[q] -= col[q] * yc;
