@@ -13,6 +13,8 @@
 // With independent points (passes = 2) the denominators come from the second
 // lattice's sums and se^2 = R/(R-1) sum_r [(num_r / sum num - 1/R)^2 + (den_r / sum den - 1/R)^2].
 // Results go to a per-term array and, when asked for, to the user-order output.
+// In an FP32 evaluation a term whose SE exceeds kRedoSe is not written by this
+// pass: it goes to the re-run list, whose FP64 pass term_finalize_redo finalizes.
 //
 // instance_logsum: one block per instance sums its terms' log-terms and se^2 in
 // a fixed order (per-thread strided partial sums, then a fixed tree), so the
@@ -39,18 +41,20 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-__global__ __launch_bounds__(64 * kFinalizeWaves) void term_finalize(
-    const InstDesc* __restrict__ insts, int n_inst, const int64_t* __restrict__ term_bases,
-    int64_t total_terms, const Aux64* __restrict__ aux64, const double* __restrict__ sums,
-    double2* __restrict__ term_res, int64_t term_base) {
-  const int64_t t = term_base + (int64_t)blockIdx.x * kFinalizeWaves + (threadIdx.x >> 6);
+// Finalize of global term t by the calling wave. allow_redo: the first pass of
+// an FP32 evaluation, which hands a term whose FP32 estimate is heavy-tailed
+// (SE above kRedoSe) to the FP64 re-run list instead of writing it.
+__device__ __forceinline__ void finalize_term(const InstDesc* __restrict__ insts, int n_inst,
+                                              const int64_t* __restrict__ term_bases,
+                                              const Aux64* __restrict__ aux64, const double* __restrict__ sums,
+                                              double2* __restrict__ term_res, int64_t t, bool allow_redo) {
   const int lane = threadIdx.x & 63;
-  if (t >= total_terms) return;   // t is the same on every lane of a wave
   const int ii = find_inst(term_bases, n_inst, t);
   const InstDesc& I = insts[ii];
   const int64_t i = t - term_bases[ii];
   const int R = I.n_shifts;
   double lt, se2;
+  bool fp32_sums = false;
   if (I.sovk[i] == 0 || aux64[t].e0 < 0.0) {   // exact, or a term that is 0 (e0 = -1)
     lt = aux64[t].lt0;
     se2 = 0.0;
@@ -70,8 +74,9 @@ __global__ __launch_bounds__(64 * kFinalizeWaves) void term_finalize(
       }
     }
     const double sn = wave_sum(pn), sd = wave_sum(pd), sc = wave_sum(pc);
-    // the log1p form needs the FP32 loop's complement sums (not kept by a promoted term's FP64 items)
-    const bool fp32_sums = I.precision == VECCHIA_FP32_LOOP && I.promote[t] == 0;
+    // the log1p form needs the FP32 loop's complement sums (not kept by the FP64
+    // items of a handed-over term)
+    fp32_sums = I.precision == VECCHIA_FP32_LOOP && I.promote[t] == 0;
     if (fp32_sums && !indep && sc < sn)
       lt = log1p(-sc / sd);
     else
@@ -98,6 +103,16 @@ __global__ __launch_bounds__(64 * kFinalizeWaves) void term_finalize(
       se2 = __builtin_nan("");
     }
   }
+  if (allow_redo && fp32_sums && se2 > kRedoSe * kRedoSe && __builtin_isfinite(lt) && __builtin_isfinite(se2)) {
+    // heavy-tailed: the few samples that carry the estimate also carry the FP32
+    // loop's rounding; the term runs again in FP64 and its pass writes it
+    if (lane == 0) {
+      I.promote[t] = 2;
+      const unsigned long long slot = atomicAdd(reinterpret_cast<unsigned long long*>(&I.pctr[2]), 1ULL);
+      if ((int64_t)slot < I.plist_cap) I.plist[I.plist_cap + slot] = (int32_t)t;
+    }
+    return;
+  }
   if (lane == 0) {
     term_res[t] = make_double2(lt, se2);
     if (I.terms_out) {
@@ -106,6 +121,26 @@ __global__ __launch_bounds__(64 * kFinalizeWaves) void term_finalize(
       I.terms_out[2 * u + 1] = sqrt(se2);
     }
   }
+}
+
+__global__ __launch_bounds__(64 * kFinalizeWaves) void term_finalize(
+    const InstDesc* __restrict__ insts, int n_inst, const int64_t* __restrict__ term_bases,
+    int64_t total_terms, const Aux64* __restrict__ aux64, const double* __restrict__ sums,
+    double2* __restrict__ term_res, int64_t term_base, int allow_redo) {
+  const int64_t t = term_base + (int64_t)blockIdx.x * kFinalizeWaves + (threadIdx.x >> 6);
+  if (t >= total_terms) return;   // t is the same on every lane of a wave
+  finalize_term(insts, n_inst, term_bases, aux64, sums, term_res, t, allow_redo != 0);
+}
+
+// The re-run list's terms after their FP64 pass, one per wave in turn.
+__global__ __launch_bounds__(64 * kFinalizeWaves) void term_finalize_redo(
+    const InstDesc* __restrict__ insts, int n_inst, const int64_t* __restrict__ term_bases,
+    const Aux64* __restrict__ aux64, const double* __restrict__ sums, double2* __restrict__ term_res,
+    const int32_t* __restrict__ list, const int64_t* __restrict__ count, int64_t cap) {
+  const int64_t n = min(*count, cap);
+  const int64_t waves = (int64_t)gridDim.x * kFinalizeWaves;
+  for (int64_t e = (int64_t)blockIdx.x * kFinalizeWaves + (threadIdx.x >> 6); e < n; e += waves)
+    finalize_term(insts, n_inst, term_bases, aux64, sums, term_res, (int64_t)list[e], false);
 }
 
 __global__ __launch_bounds__(kFinalizeThreads) void instance_logsum(const InstDesc* __restrict__ insts,
@@ -235,19 +270,33 @@ hipError_t launch_mixture_combine_many(const double* node_out, const double* log
   return e;
 }
 
-hipError_t launch_finalize(const InstDesc* d_insts, int n_inst, const int64_t* d_term_bases,
-                           int64_t total_terms, const Aux64* aux64, const double* sums,
-                           double2* term_res, hipStream_t s) {
+hipError_t launch_finalize_terms(const InstDesc* d_insts, int n_inst, const int64_t* d_term_bases,
+                                 int64_t total_terms, const Aux64* aux64, const double* sums,
+                                 double2* term_res, bool allow_redo, hipStream_t s) {
   if (n_inst <= 0) return hipSuccess;
   constexpr int64_t kPer = kMaxLaunchThreads / 64;   // terms (one wave each) per launch
   for (int64_t b = 0; b < total_terms; b += kPer) {
     const int64_t n = total_terms - b < kPer ? total_terms - b : kPer;
     const unsigned blocks = (unsigned)((n + kFinalizeWaves - 1) / kFinalizeWaves);
     hipLaunchKernelGGL(term_finalize, dim3(blocks), dim3(64 * kFinalizeWaves), 0, s, d_insts, n_inst,
-                       d_term_bases, total_terms, aux64, sums, term_res, b);
+                       d_term_bases, total_terms, aux64, sums, term_res, b, allow_redo ? 1 : 0);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
+  return hipSuccess;
+}
+
+hipError_t launch_finalize_redo(const InstDesc* d_insts, int n_inst, const int64_t* d_term_bases,
+                                const Aux64* aux64, const double* sums, double2* term_res,
+                                const int32_t* list, const int64_t* count, int64_t cap, hipStream_t s) {
+  if (n_inst <= 0 || cap <= 0) return hipSuccess;
+  const int64_t blocks = (cap + kFinalizeWaves - 1) / kFinalizeWaves;
+  hipLaunchKernelGGL(term_finalize_redo, dim3((unsigned)(blocks < 256 ? blocks : 256)), dim3(64 * kFinalizeWaves), 0,
+                     s, d_insts, n_inst, d_term_bases, aux64, sums, term_res, list, count, cap);
+  return hipGetLastError();
+}
+
+hipError_t launch_logsum(const InstDesc* d_insts, int n_inst, const double2* term_res, hipStream_t s) {
   constexpr int64_t kPerInst = kMaxLaunchThreads / kFinalizeThreads;   // instances (one block each) per launch
   for (int64_t b = 0; b < n_inst; b += kPerInst) {
     const unsigned n = (unsigned)(n_inst - b < kPerInst ? n_inst - b : kPerInst);

@@ -516,29 +516,29 @@ __device__ __forceinline__ int find_inst_q(const int64_t* __restrict__ bases, in
   return lo;
 }
 
-// Promoted terms of FP32 instances, in FP64: each wave takes the next
-// (list entry, item) pair from the work counter until the count x ipt_max pairs
-// are used up; pairs past a term's own item count are skipped. Every wave
-// leaves once the counter passes the end, so the grid always drains.
+// Handed-over terms of FP32 instances, in FP64: each wave takes the next
+// (list entry, item) pair from the work counter ctr[1] until the count x
+// ipt_max pairs are used up; pairs past a term's own item count are skipped.
+// Every wave leaves once the counter passes the end, so the grid always drains.
 __global__ __launch_bounds__(64) void qmc_promoted(const InstDesc* __restrict__ insts, int n_inst,
                                                    const int64_t* __restrict__ term_bases,
                                                    const Aux64* __restrict__ aux64, const uint64_t* __restrict__ Zg,
-                                                   double* __restrict__ sums, const int32_t* __restrict__ plist,
-                                                   int64_t* __restrict__ pctr, int plist_cap, int ipt_max) {
+                                                   double* __restrict__ sums, const int32_t* __restrict__ list,
+                                                   int64_t* __restrict__ ctr, int64_t cap, int ipt_max) {
   const int lane = threadIdx.x;
-  const int64_t count = min(pctr[0], (int64_t)plist_cap);
-  if (count == 0) return;   // nothing promoted: no wave touches the work counter
+  const int64_t count = min(ctr[0], cap);
+  if (count == 0) return;   // nothing handed over: no wave touches the work counter
   const int64_t total = count * (int64_t)ipt_max;
   for (;;) {
     unsigned long long got = 0;
-    if (lane == 0) got = atomicAdd(reinterpret_cast<unsigned long long*>(&pctr[1]), 1ULL);
+    if (lane == 0) got = atomicAdd(reinterpret_cast<unsigned long long*>(&ctr[1]), 1ULL);
     const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)got);
     const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(got >> 32));
     const int64_t v = (int64_t)(((uint64_t)hi << 32) | lo);
     if (v >= total) break;
     const int64_t e = v / ipt_max;
     const int j = (int)(v - e * ipt_max);
-    const int64_t t = uniform(plist[e]);
+    const int64_t t = uniform(list[e]);
     const int ii = uniform(find_inst_q(term_bases, n_inst, t));
     const InstDesc& I = insts[ii];
     const int ns = uniform(I.n_shifts), nc = uniform(I.n_chunks);
@@ -552,7 +552,7 @@ __global__ __launch_bounds__(64) void qmc_promoted(const InstDesc* __restrict__ 
     it.second = it.r >= ns;
     it.sr = it.second ? it.r - ns : it.r;
     it.K = uniform(I.sovk[it.i]);
-    item_f64_gen(it, aux64, Zg, sums, I.prep64 + e * I.prep64_stride);
+    item_f64_gen(it, aux64, Zg, sums, prep_f64(I, it.i));
   }
 }
 
@@ -644,13 +644,13 @@ hipError_t qmc_switch_f32_long(int K, const InstDesc* insts, const RangeDesc* ra
 }  // namespace
 
 hipError_t launch_qmc_promoted(const InstDesc* d_insts, int n_inst, const int64_t* d_term_bases, const Aux64* aux64,
-                               const uint64_t* d_Z, double* sums, const int32_t* plist, int64_t* pctr,
-                               int plist_cap, int ipt_max, hipStream_t s) {
-  if (plist_cap <= 0 || ipt_max <= 0) return hipSuccess;
-  const int64_t pairs = (int64_t)plist_cap * ipt_max;
+                               const uint64_t* d_Z, double* sums, const int32_t* list, int64_t* ctr, int64_t cap,
+                               int ipt_max, hipStream_t s) {
+  if (cap <= 0 || ipt_max <= 0) return hipSuccess;
+  const int64_t pairs = cap * (int64_t)ipt_max;
   const unsigned grid = (unsigned)(pairs < 2048 ? pairs : 2048);
   hipLaunchKernelGGL(qmc_promoted, dim3(grid), dim3(64), 0, s, d_insts, n_inst, d_term_bases, aux64, d_Z, sums,
-                     plist, pctr, plist_cap, ipt_max);
+                     list, ctr, cap, ipt_max);
   return hipGetLastError();
 }
 

@@ -49,17 +49,18 @@ __device__ __forceinline__ int find_inst(const int64_t* __restrict__ bases, int 
   return lo;
 }
 
-__global__ __launch_bounds__(64) void term_setup(const InstDesc* __restrict__ insts, int n_inst,
-                                                 const int64_t* __restrict__ term_bases,
-                                                 Aux64* __restrict__ aux64,
-                                                 Aux32* __restrict__ aux32, int64_t term_base) {
+// Set-up of global term t by the calling wave (one wave per block). redo: the
+// term of an FP32 evaluation is run again in FP64; only its FP64 rows are
+// written, in place of its FP32 rows.
+__device__ __forceinline__ void setup_term(const InstDesc* __restrict__ insts, int n_inst,
+                                           const int64_t* __restrict__ term_bases, Aux64* __restrict__ aux64,
+                                           Aux32* __restrict__ aux32, int64_t t, bool redo) {
   __shared__ double C[kMaxVars][kMaxVars + 1];
   __shared__ double px[kMaxVars], py[kMaxVars], pb[kMaxVars], pw[kMaxVars];
   __shared__ long long pslot;
   __shared__ int pv[kMaxVars];
   __shared__ double piv;
   const int lane = threadIdx.x;
-  const int64_t t = term_base + (int64_t)blockIdx.x;
   const int ii = find_inst(term_bases, n_inst, t);
   const InstDesc& I = insts[ii];
   const int64_t i = t - term_bases[ii];
@@ -148,29 +149,31 @@ __global__ __launch_bounds__(64) void term_setup(const InstDesc* __restrict__ in
     for (int c = q; c <= lane; ++c) r2 += C[lane][c] * C[lane][c];
     zc = bs / sqrt(r2);
   }
-  const bool want_promote = I.precision == VECCHIA_FP32_LOOP && __ballot(zc < kPromoteZ) != 0;
+  const bool want_promote = !redo && I.precision == VECCHIA_FP32_LOOP && __ballot(zc < kPromoteZ) != 0;
   const double nan = __builtin_nan("");
   const bool f32 = I.precision == VECCHIA_FP32_LOOP;
   const bool density = i < I.n_obs;
-  // a promoted term takes a slot of the batch's list (none left: it stays FP32)
-  bool promoted = false;
+  // a promoted term takes the next slot of the batch's list, which has room for
+  // every term; its FP64 rows replace its FP32 rows
+  bool promoted = redo;
   if (want_promote && !density && !bad && !zero && n - q >= 2) {
     if (lane == 0) pslot = (long long)atomicAdd(reinterpret_cast<unsigned long long*>(I.pctr), 1ULL);
     __syncthreads();
-    promoted = pslot < I.plist_cap;
+    promoted = true;
   }
   if (promoted && lane >= q && lane < n) {
     const int a = lane - q;
     const double laa = C[lane][lane];
-    double* row = I.prep64 + pslot * (int64_t)I.prep64_stride + (int64_t)a * (a + 1) / 2;
+    double* row = prep_f64(I, i) + (int64_t)a * (a + 1) / 2;
     for (int c = 0; c < a; ++c) row[c] = C[lane][q + c] / laa;
     row[a] = bs / laa;
   }
+  if (redo) return;
   if (f32 && lane == 0) {
     I.promote[t] = promoted ? 1 : 0;
-    if (promoted) I.plist[pslot] = (int32_t)t;
+    if (promoted && pslot < I.plist_cap) I.plist[pslot] = (int32_t)t;
   }
-  if (!density && lane >= q && lane < n) {
+  if (!density && !promoted && lane >= q && lane < n) {
     const int a = lane - q;   // row of the conditional block
     const double laa = C[lane][lane];
     const int64_t off = i * (int64_t)I.prep_stride + (int64_t)a * (a + 1) / 2;
@@ -228,6 +231,27 @@ __global__ __launch_bounds__(64) void term_setup(const InstDesc* __restrict__ in
   }
 }
 
+__global__ __launch_bounds__(64) void term_setup(const InstDesc* __restrict__ insts, int n_inst,
+                                                 const int64_t* __restrict__ term_bases,
+                                                 Aux64* __restrict__ aux64,
+                                                 Aux32* __restrict__ aux32, int64_t term_base) {
+  setup_term(insts, n_inst, term_bases, aux64, aux32, term_base + (int64_t)blockIdx.x, false);
+}
+
+// The re-run list's terms, one per wave in turn; every wave leaves once the
+// list (read once, written by the finalize before this launch) is used up.
+__global__ __launch_bounds__(64) void term_setup_redo(const InstDesc* __restrict__ insts, int n_inst,
+                                                      const int64_t* __restrict__ term_bases,
+                                                      Aux64* __restrict__ aux64, Aux32* __restrict__ aux32,
+                                                      const int32_t* __restrict__ list,
+                                                      const int64_t* __restrict__ count, int64_t cap) {
+  const int64_t n = min(*count, cap);
+  for (int64_t e = blockIdx.x; e < n; e += gridDim.x) {
+    setup_term(insts, n_inst, term_bases, aux64, aux32, (int64_t)list[e], true);
+    __syncthreads();   // the next term reuses the LDS blocks
+  }
+}
+
 }  // namespace
 
 hipError_t launch_setup(const InstDesc* d_insts, int n_inst, const int64_t* d_term_bases,
@@ -242,6 +266,15 @@ hipError_t launch_setup(const InstDesc* d_insts, int n_inst, const int64_t* d_te
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+hipError_t launch_setup_redo(const InstDesc* d_insts, int n_inst, const int64_t* d_term_bases, Aux64* aux64,
+                             Aux32* aux32, const int32_t* list, const int64_t* count, int64_t cap, hipStream_t s) {
+  if (cap <= 0) return hipSuccess;
+  const unsigned grid = (unsigned)(cap < 1024 ? cap : 1024);
+  hipLaunchKernelGGL(term_setup_redo, dim3(grid), dim3(64), 0, s, d_insts, n_inst, d_term_bases, aux64, aux32,
+                     list, count, cap);
+  return hipGetLastError();
 }
 
 }  // namespace vecchia

@@ -136,6 +136,16 @@ vecchia_status hip_error(hipError_t e, const char* what) {
 
 const char* last_error_message() { return g_err.c_str(); }
 
+void host_lattice_table(uint64_t* Z, int n) {
+  int found = 0;
+  for (uint64_t c = 2; found < n; ++c) {
+    bool prime = true;
+    for (uint64_t d = 2; d * d <= c; ++d)
+      if (c % d == 0) { prime = false; break; }
+    if (prime) Z[found++] = frac_sqrt_fixed(c);
+  }
+}
+
 const uint64_t* device_lattice_table(int device, hipError_t* err) {
   std::lock_guard<std::mutex> lk(g_dev_mu);
   auto it = g_Z.find(device);
@@ -144,13 +154,7 @@ const uint64_t* device_lattice_table(int device, hipError_t* err) {
     return it->second;
   }
   uint64_t Z[kMaxM];
-  int found = 0;
-  for (uint64_t c = 2; found < kMaxM; ++c) {
-    bool prime = true;
-    for (uint64_t d = 2; d * d <= c; ++d)
-      if (c % d == 0) { prime = false; break; }
-    if (prime) Z[found++] = frac_sqrt_fixed(c);
-  }
+  host_lattice_table(Z, kMaxM);
   uint64_t* d = nullptr;
   *err = hipMalloc(&d, sizeof(Z));
   if (*err != hipSuccess) return nullptr;
@@ -263,9 +267,9 @@ vecchia_status Batch::create(const std::vector<vecchia_plan_s*>& plans,
     const int passes = qmcs[j].flags == VECCHIA_QMC_INDEPENDENT ? 2 : 1;   // a second lattice for the denominators
     const int prec = qmcs[j].precision;
     const int nv = P->block > 0 ? P->block_nv : P->m + 1;   // variables per term, at most
-    const int stride = (int)align_up((size_t)nv * (nv + 1) / 2, prec == VECCHIA_FP32_LOOP ? 4 : 2);
-    if (prec == VECCHIA_FP32_LOOP)
-      b->prep64_stride_ = std::max(b->prep64_stride_, (int)align_up((size_t)nv * (nv + 1) / 2, 2));
+    // FP32 rows leave room for the FP64 rows of a term handed to the FP64 kernels
+    const int stride = prec == VECCHIA_FP32_LOOP ? 2 * (int)align_up((size_t)nv * (nv + 1) / 2, 2)
+                                                 : (int)align_up((size_t)nv * (nv + 1) / 2, 2);
     InstDesc& d = b->desc_[j];
     std::memset(&d, 0, sizeof(d));
     d.xs = P->d_xs;
@@ -370,32 +374,19 @@ vecchia_status Batch::create(const std::vector<vecchia_plan_s*>& plans,
   take(sizeof(int64_t) * n);
   take(prep);
   if (b->any_f32_) {
-    // promoted terms (FP32 instances): flags, list, counters and a bounded FP64 row buffer
-    b->plist_cap_ = (int32_t)std::min<int64_t>(tb, std::max<int64_t>(256, tb / 8));
+    // terms handed to FP64 (FP32 instances): flags, two lists with room for
+    // every term, and their counters
+    b->plist_cap_ = (int32_t)tb;
     take(sizeof(int32_t) * tb);
-    take(sizeof(int32_t) * b->plist_cap_);
-    take(sizeof(int64_t) * 2);
-    take(sizeof(double) * (size_t)b->plist_cap_ * b->prep64_stride_);
+    take(sizeof(int32_t) * 2 * (size_t)tb);
+    take(sizeof(int64_t) * 4);
   }
   b->ws_bytes_ = off;
   *out = std::move(b);
   return VECCHIA_OK;
 }
 
-vecchia_status Batch::allocate() {
-  if (d_ws_ || d_desc_) return VECCHIA_OK;
-  hipError_t e;
-  d_Z_ = device_lattice_table(device_, &e);
-  if (!d_Z_) return hip_error(e, "lattice table");
-  char* base = ext_ws_;
-  if (!base) {
-    e = hipMalloc(&d_ws_, ws_bytes_);
-    if (e != hipSuccess) {
-      d_ws_ = nullptr;
-      return hip_error(e, "workspace allocation");
-    }
-    base = d_ws_;
-  }
+void Batch::carve(char* base) {
   const int n = (int)plans_.size();
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -414,10 +405,10 @@ vecchia_status Batch::allocate() {
   d_prep_ = take(prep_bytes_);
   if (any_f32_) {
     d_promote_ = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * total_terms_));
-    d_plist_ = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * plist_cap_));
-    d_pctr_ = reinterpret_cast<int64_t*>(take(sizeof(int64_t) * 2));
-    d_prep64_ = reinterpret_cast<double*>(take(sizeof(double) * (size_t)plist_cap_ * prep64_stride_));
+    d_plist_ = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * 2 * (size_t)total_terms_));
+    d_pctr_ = reinterpret_cast<int64_t*>(take(sizeof(int64_t) * 4));
   }
+  ipt_max_ = 0;
   for (int j = 0; j < n; ++j) {
     desc_[j].prep = d_prep_ + prep_off_[j];
     desc_[j].bad_term = d_bad_ + j;
@@ -425,11 +416,27 @@ vecchia_status Batch::allocate() {
     desc_[j].promote = f32 ? d_promote_ : nullptr;
     desc_[j].plist = f32 ? d_plist_ : nullptr;
     desc_[j].pctr = f32 ? d_pctr_ : nullptr;
-    desc_[j].prep64 = f32 ? d_prep64_ : nullptr;
-    desc_[j].prep64_stride = prep64_stride_;
     desc_[j].plist_cap = plist_cap_;
     if (f32) ipt_max_ = std::max(ipt_max_, desc_[j].passes * desc_[j].n_shifts * desc_[j].n_chunks);
   }
+}
+
+vecchia_status Batch::allocate() {
+  if (d_ws_ || d_desc_) return VECCHIA_OK;
+  hipError_t e;
+  d_Z_ = device_lattice_table(device_, &e);
+  if (!d_Z_) return hip_error(e, "lattice table");
+  char* base = ext_ws_;
+  if (!base) {
+    e = hipMalloc(&d_ws_, ws_bytes_);
+    if (e != hipSuccess) {
+      d_ws_ = nullptr;
+      return hip_error(e, "workspace allocation");
+    }
+    base = d_ws_;
+  }
+  const int n = (int)plans_.size();
+  carve(base);
   if (!ext_stage_) {
     e = hipHostMalloc(reinterpret_cast<void**>(&h_stage_), sizeof(InstDesc) * n * kRing, hipHostMallocDefault);
     if (e != hipSuccess) {
@@ -453,11 +460,11 @@ vecchia_status Batch::allocate() {
   return VECCHIA_OK;
 }
 
-vecchia_status Batch::enqueue(hipStream_t s) {
+vecchia_status Batch::enqueue(hipStream_t s, bool allow_profile) {
   const int n = (int)plans_.size();
-  const bool prof = profiling_enabled();
+  const bool prof = allow_profile && profiling_enabled();
   hipError_t e = launch_fill_i64(d_bad_, n, INT64_MAX, s);
-  if (e == hipSuccess && any_f32_) e = launch_fill_i64(d_pctr_, 2, 0, s);
+  if (e == hipSuccess && any_f32_) e = launch_fill_i64(d_pctr_, 4, 0, s);
   if (e == hipSuccess)
     e = launch_setup(d_desc_, n, d_term_bases_, total_terms_, d_aux64_, d_aux32_, s);
   // fork: side streams start after the setup kernel
@@ -487,29 +494,38 @@ vecchia_status Batch::enqueue(hipStream_t s) {
     e = hipEventRecord(join_ev_[k], side_[k]);
     if (e == hipSuccess) e = hipStreamWaitEvent(s, join_ev_[k], 0);
   }
-  // the FP32 instances' promoted terms, in FP64 (a short persistent grid that
-  // finds nothing to do when no term was promoted)
-  if (e == hipSuccess && any_f32_ && ipt_max_ > 0)
+  // FP32 instances: the terms promoted at set-up, in FP64 (a short persistent
+  // grid that finds nothing to do when no term was promoted)
+  const bool redo = any_f32_ && ipt_max_ > 0;
+  if (e == hipSuccess && redo)
     e = launch_qmc_promoted(d_desc_, n, d_term_bases_, d_aux64_, d_Z_, d_sums_, d_plist_, d_pctr_, plist_cap_,
                             ipt_max_, s);
   if (e == hipSuccess)
-    e = launch_finalize(d_desc_, n, d_term_bases_, total_terms_, d_aux64_, d_sums_, d_term_res_, s);
+    e = launch_finalize_terms(d_desc_, n, d_term_bases_, total_terms_, d_aux64_, d_sums_, d_term_res_, redo, s);
+  // then the terms whose FP32 estimate the finalize found heavy-tailed: FP64
+  // rows, FP64 items and their finalize (three grids that exit at once when
+  // the list is empty)
+  if (e == hipSuccess && redo)
+    e = launch_setup_redo(d_desc_, n, d_term_bases_, d_aux64_, d_aux32_, d_plist_ + plist_cap_, d_pctr_ + 2,
+                          plist_cap_, s);
+  if (e == hipSuccess && redo)
+    e = launch_qmc_promoted(d_desc_, n, d_term_bases_, d_aux64_, d_Z_, d_sums_, d_plist_ + plist_cap_, d_pctr_ + 2,
+                            plist_cap_, ipt_max_, s);
+  if (e == hipSuccess && redo)
+    e = launch_finalize_redo(d_desc_, n, d_term_bases_, d_aux64_, d_sums_, d_term_res_, d_plist_ + plist_cap_,
+                             d_pctr_ + 2, plist_cap_, s);
+  if (e == hipSuccess) e = launch_logsum(d_desc_, n, d_term_res_, s);
   if (e != hipSuccess) return hip_error(e, "kernel launch");
   return VECCHIA_OK;
 }
 
-vecchia_status Batch::run(const double* x_dev, const double* scales, const vecchia_cov* covs,
-                          double* out_dev, double* terms_dev, const uint64_t* seeds, hipStream_t s) {
+vecchia_status Batch::fill_desc(const double* x_dev, const double* scales, const vecchia_cov* covs,
+                                double* out_dev, double* terms_dev, const uint64_t* seeds,
+                                std::vector<InstDesc>* out) const {
   const int n = (int)plans_.size();
-  if (!x_dev || !out_dev) return set_error(VECCHIA_E_INVALID, "x_dev and out_dev must be device pointers");
-  int dev = 0;
-  hipGetDevice(&dev);
-  if (dev != device_) return set_error(VECCHIA_E_INVALID, "current device differs from the batch's device");
-  // device buffers first: the descriptors below carry their addresses
-  vecchia_status st = allocate();
-  if (st != VECCHIA_OK) return st;
   int64_t xo = 0;
-  std::vector<InstDesc> d = desc_;
+  std::vector<InstDesc>& d = *out;
+  d = desc_;
   for (int j = 0; j < n; ++j) {
     vecchia_plan_s* P = plans_[j];
     const vecchia_cov c = covs ? covs[j] : P->cov;
@@ -543,6 +559,22 @@ vecchia_status Batch::run(const double* x_dev, const double* scales, const vecch
         !d_Z_ || (any_f32_ && !d_aux32_))
       return set_error(VECCHIA_E_HIP, "internal error: incomplete device descriptor");
   }
+  return VECCHIA_OK;
+}
+
+vecchia_status Batch::run(const double* x_dev, const double* scales, const vecchia_cov* covs,
+                          double* out_dev, double* terms_dev, const uint64_t* seeds, hipStream_t s) {
+  const int n = (int)plans_.size();
+  if (!x_dev || !out_dev) return set_error(VECCHIA_E_INVALID, "x_dev and out_dev must be device pointers");
+  int dev = 0;
+  hipGetDevice(&dev);
+  if (dev != device_) return set_error(VECCHIA_E_INVALID, "current device differs from the batch's device");
+  // device buffers first: the descriptors below carry their addresses
+  vecchia_status st = allocate();
+  if (st != VECCHIA_OK) return st;
+  std::vector<InstDesc> d;
+  st = fill_desc(x_dev, scales, covs, out_dev, terms_dev, seeds, &d);
+  if (st != VECCHIA_OK) return st;
   hipError_t e = hipSuccess;
   if (!tables_uploaded_) {
     // host tables live as long as the batch, so the asynchronous copy is safe
@@ -583,7 +615,7 @@ vecchia_status Batch::run(const double* x_dev, const double* scales, const vecch
       hipGraph_t g = nullptr;
       e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
       if (e == hipSuccess) {
-        st = enqueue(s);
+        st = enqueue(s, true);
         hipError_t e2 = hipStreamEndCapture(s, &g);
         if (st == VECCHIA_OK && e2 == hipSuccess && g) {
           e2 = hipGraphInstantiate(&graph_exec_, g, nullptr, nullptr, 0);
@@ -602,7 +634,7 @@ vecchia_status Batch::run(const double* x_dev, const double* scales, const vecch
     e = hipGraphLaunch(graph_exec_, s);
     if (e != hipSuccess) return hip_error(e, "graph launch");
   } else {
-    st = enqueue(s);
+    st = enqueue(s, true);
     if (st != VECCHIA_OK) return st;
     ++eager_runs_;
   }

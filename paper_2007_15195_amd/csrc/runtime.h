@@ -22,6 +22,8 @@ hipError_t profile_events(hipEvent_t* a, hipEvent_t* b);
 void profile_record(int K, int precision, hipEvent_t a, hipEvent_t b, int64_t sov_steps);
 vecchia_status hip_error(hipError_t e, const char* what);
 const uint64_t* device_lattice_table(int device, hipError_t* err);
+// Generators Z_j of the first n primes, computed on the host.
+void host_lattice_table(uint64_t* Z, int n);
 // Generators Z_j of the first n primes (n >= 1), cached per device and grown on
 // demand; the returned table stays valid until the process ends.
 const uint64_t* device_lattice_table_n(int device, int n, hipError_t* err);
@@ -80,7 +82,10 @@ class Batch {
     int64_t sov_steps;   // sum over the launch's terms of n_shifts * n_points * K
   };
   vecchia_status allocate();
-  vecchia_status enqueue(hipStream_t s);
+  void carve(char* base);   // workspace arrays at base (the layout of create())
+  vecchia_status fill_desc(const double* x_dev, const double* scales, const vecchia_cov* covs, double* out_dev,
+                           double* terms_dev, const uint64_t* seeds, std::vector<InstDesc>* out) const;
+  vecchia_status enqueue(hipStream_t s, bool allow_profile);
 
   std::vector<vecchia_plan_s*> plans_;
   std::vector<vecchia_qmc> qmcs_;
@@ -107,12 +112,10 @@ class Batch {
   int64_t* d_bad_ = nullptr;
   char* d_prep_ = nullptr;
   const uint64_t* d_Z_ = nullptr;
-  // promoted terms of FP32 instances (see InstDesc)
+  // terms of FP32 instances handed to FP64 (see InstDesc)
   int32_t* d_promote_ = nullptr;
   int32_t* d_plist_ = nullptr;
   int64_t* d_pctr_ = nullptr;
-  double* d_prep64_ = nullptr;
-  int32_t prep64_stride_ = 0;
   int32_t plist_cap_ = 0;
   int32_t ipt_max_ = 0;
 

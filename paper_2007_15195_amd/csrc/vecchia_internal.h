@@ -11,6 +11,7 @@ namespace vecchia {
 constexpr int kMaxM = VECCHIA_MAX_M;   // conditioning-set size limit
 constexpr int kMaxVars = kMaxM + 1;    // variables per term
 constexpr double kPromoteZ = -4.0;     // FP32 instances: terms with a limit below this many SDs run in FP64
+constexpr double kRedoSe = 0.02;       // FP32 instances: terms whose log-term SE exceeds this run again in FP64
 // Chains of up to this many steps run fully unrolled with y in registers;
 // longer ones (up to kMaxM) run in the general kernel with y in LDS.
 constexpr int kMaxUnrolledK = 31;
@@ -32,18 +33,22 @@ struct InstDesc {
   double* out;             // {log F, SE}
   double* terms_out;       // D x 2 user order, or null
   void* prep;              // per-term scaled Cholesky rows (double or float), term 0
-  // FP32 instances: terms with a chain limit below kPromoteZ standard deviations
-  // (of the variable given the observed sites) are evaluated in FP64 instead
-  // (the FP32 items of such a term exit at once).
-  // promote[t] (global term index) is 1 for them; their FP64 rows sit at
-  // prep64 + slot * prep64_stride, slot = their position in plist (at most
-  // plist_cap); pctr = {promoted count, work counter}. Shared by the batch.
+  // FP32 instances hand some terms to FP64 kernels on the same lattice points:
+  //  - at set-up, terms with a chain limit below kPromoteZ standard deviations
+  //    (of the variable given the observed sites); their FP32 items exit at once;
+  //  - after the FP32 pass, terms whose estimate is heavy-tailed (SE of the
+  //    log-term above kRedoSe), evaluated again.
+  // promote[t] (global term index) is 0, 1 (set-up) or 2 (re-run). A handed-over
+  // term's FP64 rows take the place of its FP32 rows: prep_f64(I, i). plist holds
+  // two lists of global term indices, plist_cap (= the batch's term count) each:
+  // [0, cap) the set-up promotions, [cap, 2 cap) the re-runs; pctr = {count,
+  // work counter} of each. Every qualifying term gets a slot, so a term's value
+  // depends only on its instance. Shared by the batch.
   int32_t* promote;
-  double* prep64;
   int32_t* plist;
   int64_t* pctr;
-  int32_t prep64_stride;
   int32_t plist_cap;
+  int32_t pad0_;
   int64_t D;
   int64_t n_terms;         // terms: D, or the number of groups of a block plan
   // block plans (joint terms, Section 3.2): term i's variables are
@@ -63,7 +68,7 @@ struct InstDesc {
   int32_t passes;          // 2: the denominators come from a second lattice (VECCHIA_QMC_INDEPENDENT)
   int32_t pad_;
   uint64_t seed;
-  int32_t prep_stride;     // elements per term in prep
+  int32_t prep_stride;     // elements per term in prep (FP32 instances: even, room for the FP64 rows)
   int32_t precision;       // VECCHIA_FP64 / VECCHIA_FP32_LOOP
   int32_t chunk_points;    // lattice points per work item (a multiple of 64)
   int32_t n_chunks;        // ceil(n_points / chunk_points)
@@ -105,6 +110,12 @@ struct KnnGrid {
 // Plans with more points than this search neighbours through the grid.
 constexpr int64_t kKnnGridMinD = 16384;
 
+// FP64 rows of plan term i of an FP32 instance, in place of its FP32 rows
+// (a term handed to the FP64 kernels; row a at offset a (a + 1) / 2).
+__host__ __device__ inline double* prep_f64(const InstDesc& I, int64_t i) {
+  return reinterpret_cast<double*>(I.prep) + i * (int64_t)(I.prep_stride / 2);
+}
+
 // Launchers (kernels_*.hip).
 // group > 1: query i's candidates are j < i - i mod group (no grid then).
 hipError_t launch_knn(const double* xs, const double* ys, int64_t D, int m, int32_t* nbr,
@@ -112,16 +123,21 @@ hipError_t launch_knn(const double* xs, const double* ys, int64_t D, int m, int3
 hipError_t launch_fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t s);
 hipError_t launch_setup(const InstDesc* d_insts, int n_inst, const int64_t* d_term_bases,
                         int64_t total_terms, Aux64* aux64, Aux32* aux32, hipStream_t s);
+// The FP64 rows of the terms on a device-side list (count at *count, at most
+// cap entries): the re-runs of an FP32 evaluation. A persistent grid that
+// finds nothing to do when the list is empty.
+hipError_t launch_setup_redo(const InstDesc* d_insts, int n_inst, const int64_t* d_term_bases, Aux64* aux64,
+                             Aux32* aux32, const int32_t* list, const int64_t* count, int64_t cap, hipStream_t s);
 // block: the launch's instances are block plans (denominator split per term).
 hipError_t launch_qmc(int K, int precision, bool block, const InstDesc* d_insts, const RangeDesc* d_ranges,
                       int n_ranges, int64_t n_items, const Aux64* aux64, const Aux32* aux32,
                       const uint64_t* d_Z, double* sums, hipStream_t s);
-// The promoted terms of FP32 instances in FP64: a persistent grid takes
-// (term, item) pairs from the device-side list (pctr[0] entries, at most
-// plist_cap; ipt_max items per term at most) until none is left.
+// The handed-over terms of FP32 instances in FP64: a persistent grid takes
+// (term, item) pairs from a device-side list (ctr[0] entries, at most cap;
+// ipt_max items per term at most; ctr[1] is the work counter) until none is left.
 hipError_t launch_qmc_promoted(const InstDesc* d_insts, int n_inst, const int64_t* d_term_bases, const Aux64* aux64,
-                               const uint64_t* d_Z, double* sums, const int32_t* plist, int64_t* pctr,
-                               int plist_cap, int ipt_max, hipStream_t s);
+                               const uint64_t* d_Z, double* sums, const int32_t* list, int64_t* ctr,
+                               int64_t cap, int ipt_max, hipStream_t s);
 // Scale-mixture quadrature weights (log), passed by value to the combine kernel.
 constexpr int kMaxMixNodes = 64;
 constexpr int kMixSearch = VECCHIA_MIX_SEARCH_NODES;
@@ -138,8 +154,15 @@ hipError_t launch_mixture_combine(const double* node_out, const MixWeights& mw, 
 // the log G and the root sum of squares of the SEs.
 hipError_t launch_mixture_combine_many(const double* node_out, const double* logw, int n_nodes, int64_t n_mix,
                                        double* out, double* total, hipStream_t s);
-hipError_t launch_finalize(const InstDesc* d_insts, int n_inst, const int64_t* d_term_bases,
-                           int64_t total_terms, const Aux64* aux64, const double* sums,
-                           double2* term_res, hipStream_t s);
+// term_finalize over every term, then (redo_list non-null) over the re-run list
+// after its FP64 pass, then the per-instance sums. Without a list the first
+// pass hands nothing over.
+hipError_t launch_finalize_terms(const InstDesc* d_insts, int n_inst, const int64_t* d_term_bases,
+                                 int64_t total_terms, const Aux64* aux64, const double* sums,
+                                 double2* term_res, bool allow_redo, hipStream_t s);
+hipError_t launch_finalize_redo(const InstDesc* d_insts, int n_inst, const int64_t* d_term_bases,
+                                const Aux64* aux64, const double* sums, double2* term_res,
+                                const int32_t* list, const int64_t* count, int64_t cap, hipStream_t s);
+hipError_t launch_logsum(const InstDesc* d_insts, int n_inst, const double2* term_res, hipStream_t s);
 
 }  // namespace vecchia

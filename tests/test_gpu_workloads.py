@@ -178,6 +178,70 @@ def test_serving_mix_equals_standalone_calls():
         V.vecchia_plan_destroy(p)
 
 
+def test_served_requests_match_the_oracle():
+    # three requests shaped like the serving stream's, served in a mix with
+    # larger ones, against the oracle: one with a covariance override, one with
+    # a scale factor (eq. (9)'s Phi_D(x / r)), one with m = 30; in FP64 (1e-10)
+    # and FP32 (1e-2 relative in log F)
+    import time
+    torch = torch_cuda()
+    from paper_2007_15195_amd import vecchia as V
+    rng = np.random.default_rng(515)
+    specs = [  # (D, m, range of the plan, override or None, scale, N)
+        (1500, 12, 0.1, W.Cov(W.COV_MATERN, 1.5, 1.3, 0.23, 1e-8), 1.0, 2048),
+        (1200, 8, 0.1, None, 2.7183, 2048),
+        (900, 30, 0.15, W.Cov(W.COV_MATERN, 1.5, 1.0, 0.05, 1e-8), 1.4142, 4096),
+    ]
+    checked = []
+    for D, m, rho, ov, scale, N in specs:
+        locs = rng.random((D, 2))
+        x = rng.normal(1.5, 0.5, D)
+        checked.append(W.Instance(f"served_D{D}_m{m}", locs, x, m, W.ORDER_MAXMIN,
+                                  W.Cov(W.COV_MATERN, 1.5, 1.0, rho, 1e-8), W.QMC(N, 8, 600 + D, W.PREC_FP64),
+                                  scale=scale))
+    st = W.serving_stream(n_plans=3, n_requests=6, d_min=5000, d_max=20000)
+    plans = [V.vecchia_plan(i.locs, i.ordering, i.m, i.cov) for i in checked]
+    others = [V.vecchia_plan(p.locs, p.ordering, p.m, p.cov) for p in st.plans]
+    xs = [torch.tensor(i.x, dtype=torch.float64, device="cuda") for i in checked]
+    xo = [torch.tensor(r.x, dtype=torch.float64, device="cuda") for r in st.requests]
+    torch.cuda.synchronize()
+    srv = V.vecchia_server_create(4 << 30, 8)
+    tickets = []
+    for prec in (V.VECCHIA_FP64, V.VECCHIA_FP32_LOOP):
+        for k, (inst, (_, _, _, ov, _, _)) in enumerate(zip(checked, specs)):
+            q = V.make_qmc(inst.qmc.n_points, 8, inst.qmc.seed, prec)
+            tickets.append(((prec, k), V.vecchia_submit(srv, plans[k], xs[k], q, scale=inst.scale,
+                                                        cov_override=ov)))
+            r = st.requests[len(tickets) % len(st.requests)]
+            tickets.append((None, V.vecchia_submit(srv, others[r.plan_id], xo[len(tickets) % len(xo)], r.qmc,
+                                                   scale=r.scale, cov_override=r.cov)))
+    got = {}
+    t_end = time.time() + 120
+    while len(got) < len(tickets) and time.time() < t_end:
+        for j, (key, t) in enumerate(tickets):
+            if j not in got:
+                res = V.vecchia_poll(srv, t)
+                if res is not None:
+                    got[j] = (key, res)
+        time.sleep(0.001)
+    V.vecchia_server_destroy(srv)
+    assert len(got) == len(tickets)
+    res = {key: r for key, r in got.values() if key is not None}
+    for k, (inst, (_, _, _, ov, _, _)) in enumerate(zip(checked, specs)):
+        c = ov or inst.cov
+        o = oracle.logcdf(inst.locs, inst.x, inst.m, c.family, c.nu, c.sigma2, c.range, c.nugget, inst.ordering,
+                          inst.qmc.n_points, 8, inst.qmc.seed, scale=inst.scale,
+                          processes=oracle.vecchia.default_processes())
+        lf64, se64, _ = res[(V.VECCHIA_FP64, k)]
+        lf32, se32, _ = res[(V.VECCHIA_FP32_LOOP, k)]
+        print(inst.name, "oracle", o["logF"], "fp64", lf64, "fp32", lf32, flush=True)
+        assert abs(lf64 - o["logF"]) <= 1e-10
+        assert abs(se64 - o["se"]) <= 1e-6 * o["se"]
+        assert abs(lf32 - o["logF"]) <= FP32_REL_TOL * abs(o["logF"])
+    for p in plans + others:
+        V.vecchia_plan_destroy(p)
+
+
 def test_launch_split_beyond_the_work_item_limit():
     # 64-point chunks on 70,000 terms x 8 shifts x 4096 points give 35.8M work
     # items (one wave each): more than one launch can hold (2^32 work-items), so
