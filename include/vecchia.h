@@ -251,6 +251,24 @@ vecchia_status vecchia_logcdf(vecchia_plan_t plan, const double* x_dev, double s
                               const vecchia_cov* cov_override, const vecchia_qmc* q,
                               double* out_dev, double* terms_dev, void* hip_stream);
 
+/* As vecchia_logcdf, for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * The evaluation's workspace lives in a static device array of
+ * VECCHIA_NOALLOC_SCRATCH_BYTES per GPU (held from the first call on that GPU
+ * until the process ends); the call allocates no device or pinned memory,
+ * creates no stream or event, and enqueues only kernels on hip_stream (the
+ * descriptors travel as kernel arguments). Arguments, outputs and results are
+ * those of vecchia_logcdf, bit for bit. Every call on a GPU shares that GPU's
+ * array: calls that overlap on one GPU (on any streams) race and must be
+ * ordered. A covariance block that is not positive definite makes the outputs
+ * NaN; it is not recorded for vecchia_plan_status.
+ * Errors: INVALID (bad arguments; a workspace larger than the array, with the
+ * bytes needed in the message; nothing enqueued), HIP. */
+#define VECCHIA_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+vecchia_status vecchia_logcdf_noalloc(vecchia_plan_t plan, const double* x_dev, double scale,
+                                      const vecchia_cov* cov_override, const vecchia_qmc* q,
+                                      double* out_dev, double* terms_dev, void* hip_stream);
+
 /* Wait for the plan's last call and report whether every term factored:
  * OK, or NOT_PD with the first failing plan-order term in *bad_term
  * (-1 when OK) and in the error message. */

@@ -35,6 +35,7 @@ SOURCES = [
     "mixture.cpp",
     "fullsov.hip",
     "probe.hip",
+    "noalloc.hip",
 ]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-function",

@@ -645,6 +645,38 @@ vecchia_status Batch::run(const double* x_dev, const double* scales, const vecch
   return VECCHIA_OK;
 }
 
+vecchia_status Batch::run_noalloc(char* ws, const uint64_t* Z_dev, const double* x_dev, const double* scales,
+                                  const vecchia_cov* covs, double* out_dev, double* terms_dev,
+                                  const uint64_t* seeds, hipStream_t s) {
+  if (!x_dev || !out_dev) return set_error(VECCHIA_E_INVALID, "x_dev and out_dev must be device pointers");
+  int dev = 0;
+  hipGetDevice(&dev);
+  if (dev != device_) return set_error(VECCHIA_E_INVALID, "current device differs from the batch's device");
+  if (d_ws_ || h_stage_) return set_error(VECCHIA_E_INVALID, "internal error: batch already holds resources");
+  carve(ws);
+  d_Z_ = Z_dev;
+  std::vector<InstDesc> d;
+  vecchia_status st = fill_desc(x_dev, scales, covs, out_dev, terms_dev, seeds, &d);
+  if (st != VECCHIA_OK) return st;
+  // the workspace opens with the descriptors, the term bases and the ranges:
+  // one host image of that header, written by kernels that take it by value
+  const int n = (int)plans_.size();
+  const size_t hdr = (size_t)(reinterpret_cast<char*>(d_aux64_) - ws);
+  std::vector<char> img(hdr, 0);
+  std::memcpy(img.data(), d.data(), sizeof(InstDesc) * n);
+  std::memcpy(img.data() + (reinterpret_cast<char*>(d_term_bases_) - ws), term_bases_.data(),
+              sizeof(int64_t) * (n + 1));
+  if (!ranges_.empty())
+    std::memcpy(img.data() + (reinterpret_cast<char*>(d_ranges_) - ws), ranges_.data(),
+                sizeof(RangeDesc) * ranges_.size());
+  hipError_t e = launch_store_bytes(ws, img.data(), hdr, s);
+  if (e != hipSuccess) return hip_error(e, "descriptor store");
+  st = enqueue(s, false);
+  if (st != VECCHIA_OK) return st;
+  last_stream_ = s;
+  return VECCHIA_OK;
+}
+
 vecchia_status Batch::status(std::vector<int64_t>* bad) {
   const int n = (int)plans_.size();
   bad->assign(n, -1);

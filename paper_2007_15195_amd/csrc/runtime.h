@@ -48,6 +48,14 @@ class Batch {
   vecchia_status run(const double* x_dev, const double* scales, const vecchia_cov* covs,
                      double* out_dev, double* terms_dev, const uint64_t* seeds, hipStream_t s);
   vecchia_status status(std::vector<int64_t>* bad);  // waits for the last run
+  // As run(), on a caller-provided device workspace only: ws (workspace_bytes(),
+  // 256-byte aligned) and Z_dev (the lattice generators, kMaxM entries). Nothing
+  // is allocated: descriptors and tables reach the device as kernel arguments,
+  // every launch runs on s, and no event, graph or timing hook is used. The
+  // batch must not have run() before; NOT_PD shows only as NaN outputs.
+  vecchia_status run_noalloc(char* ws, const uint64_t* Z_dev, const double* x_dev, const double* scales,
+                             const vecchia_cov* covs, double* out_dev, double* terms_dev, const uint64_t* seeds,
+                             hipStream_t s);
   // Run on caller-owned memory instead of allocating: ws (workspace_bytes(),
   // 256-byte aligned, device) and stage (n() descriptors, pinned host, not
   // reused by the caller before this batch's work has been consumed).

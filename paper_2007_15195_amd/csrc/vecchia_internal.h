@@ -121,6 +121,9 @@ __host__ __device__ inline double* prep_f64(const InstDesc& I, int64_t i) {
 hipError_t launch_knn(const double* xs, const double* ys, int64_t D, int m, int32_t* nbr,
                       int32_t* kcnt, const KnnGrid* grid, hipStream_t s, int group = 1);
 hipError_t launch_fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t s);
+// Copies `bytes` bytes of host memory to dst (device, 8-byte aligned) by kernels
+// that take them as arguments (no staging buffer, no memcpy node).
+hipError_t launch_store_bytes(void* dst, const void* src_host, size_t bytes, hipStream_t s);
 hipError_t launch_setup(const InstDesc* d_insts, int n_inst, const int64_t* d_term_bases,
                         int64_t total_terms, Aux64* aux64, Aux32* aux32, hipStream_t s);
 // The FP64 rows of the terms on a device-side list (count at *count, at most

@@ -27,10 +27,12 @@ VECCHIA_MAX_M = 63
 VECCHIA_MAX_SHIFTS = 65536
 VECCHIA_MAX_POINTS = 1 << 30
 VECCHIA_QMC_INDEPENDENT = 1
+VECCHIA_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 EXPORTED = [
     "vecchia_last_error", "vecchia_order", "vecchia_plan", "vecchia_plan_from_cov",
-    "vecchia_replan", "vecchia_plan_info", "vecchia_plan_neighbours", "vecchia_logcdf", "vecchia_plan_status",
+    "vecchia_replan", "vecchia_plan_info", "vecchia_plan_neighbours", "vecchia_logcdf", "vecchia_logcdf_noalloc",
+    "vecchia_plan_status",
     "vecchia_plan_destroy", "vecchia_batch_create", "vecchia_batch_logcdf", "vecchia_batch_status",
     "vecchia_batch_destroy", "vecchia_server_create", "vecchia_submit", "vecchia_poll",
     "vecchia_server_destroy", "vecchia_profile_enable", "vecchia_profile_read", "vecchia_profile_reset",
@@ -102,6 +104,8 @@ def lib():
         "vecchia_plan_neighbours": [c_void_p, c_void_p, c_void_p],
         "vecchia_logcdf": [c_void_p, c_void_p, c_double, c_void_p, POINTER(vecchia_qmc), c_void_p,
                            c_void_p, c_void_p],
+        "vecchia_logcdf_noalloc": [c_void_p, c_void_p, c_double, c_void_p, POINTER(vecchia_qmc), c_void_p,
+                                   c_void_p, c_void_p],
         "vecchia_plan_status": [c_void_p, POINTER(c_int64)],
         "vecchia_plan_destroy": [c_void_p],
         "vecchia_batch_create": [c_void_p, c_int32, c_void_p, POINTER(c_void_p)],
@@ -308,6 +312,19 @@ def vecchia_logcdf(plan: int, x, qmc, out, scale: float = 1.0, cov_override=None
                                 _dev_ptr(out, 2, "out"),
                                 None if terms is None else _dev_ptr(terms, 2 * plan_n_terms(plan), "terms"),
                                 _stream_ptr(stream)))
+
+
+def vecchia_logcdf_noalloc(plan: int, x, qmc, out, scale: float = 1.0, cov_override=None, terms=None,
+                           stream=None) -> None:
+    """vecchia_logcdf on the library's static per-GPU scratch array (no allocation)."""
+    D, _ = vecchia_plan_info(plan)
+    q = as_qmc(qmc)
+    c = as_cov(cov_override)
+    _check(lib().vecchia_logcdf_noalloc(plan, _dev_ptr(x, D, "x"), float(scale),
+                                        None if c is None else ctypes.addressof(c), byref(q),
+                                        _dev_ptr(out, 2, "out"),
+                                        None if terms is None else _dev_ptr(terms, 2 * plan_n_terms(plan), "terms"),
+                                        _stream_ptr(stream)))
 
 
 def vecchia_plan_status(plan: int) -> int:
