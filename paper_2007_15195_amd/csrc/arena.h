@@ -25,6 +25,11 @@ struct Arena {
     }
     return false;
   }
+  size_t largest_free() const {
+    size_t m = 0;
+    for (const auto& kv : free) m = kv.second > m ? kv.second : m;
+    return m;
+  }
   void release(size_t off, size_t n) {
     n = (n + 255) / 256 * 256;
     auto it = free.emplace(off, n).first;

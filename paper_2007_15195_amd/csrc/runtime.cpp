@@ -223,7 +223,7 @@ int chunk_points_for(int m, int precision, int n_points) {
 Batch::~Batch() {
   if (graph_exec_) hipGraphExecDestroy(graph_exec_);
   for (int k = 0; k < kSideStreams; ++k) {
-    if (side_[k]) {
+    if (side_[k] && own_side_) {
       hipStreamSynchronize(side_[k]);
       hipStreamDestroy(side_[k]);
     }
@@ -450,10 +450,14 @@ vecchia_status Batch::allocate() {
   }
   e = hipEventCreateWithFlags(&done_ev_, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&fork_ev_, hipEventDisableTiming);
-  // batches running on caller-provided resources (server requests) keep every
-  // launch on the caller's stream
-  for (int k = 0; k < kSideStreams && e == hipSuccess && !ext_stage_; ++k) {
-    e = hipStreamCreateWithFlags(&side_[k], hipStreamNonBlocking);
+  // batches on caller-provided resources use the caller's side streams, if
+  // any, and otherwise keep every launch on the caller's stream
+  own_side_ = !ext_stage_;
+  for (int k = 0; k < kSideStreams && e == hipSuccess && (own_side_ || ext_side_[0]); ++k) {
+    if (own_side_)
+      e = hipStreamCreateWithFlags(&side_[k], hipStreamNonBlocking);
+    else
+      side_[k] = ext_side_[k] ? ext_side_[k] : ext_side_[0];
     if (e == hipSuccess) e = hipEventCreateWithFlags(&join_ev_[k], hipEventDisableTiming);
   }
   if (e != hipSuccess) return hip_error(e, "streams and events");
@@ -537,7 +541,7 @@ vecchia_status Batch::fill_desc(const double* x_dev, const double* scales, const
     }
     const double sc = scales ? scales[j] : 1.0;
     if (!(std::isfinite(sc) && sc > 0)) return set_error(VECCHIA_E_INVALID, "scale must be finite and > 0");
-    d[j].x = !x_off_.empty() ? x_dev + x_off_[j] : shared_x_ ? x_dev : x_dev + xo;
+    d[j].x = !x_ptrs_.empty() ? x_ptrs_[j] : !x_off_.empty() ? x_dev + x_off_[j] : shared_x_ ? x_dev : x_dev + xo;
     d[j].out = out_dev + 2 * j;
     d[j].terms_out = terms_dev;
     d[j].inv_scale = 1.0 / sc;

@@ -59,10 +59,17 @@ class Batch {
   // Run on caller-owned memory instead of allocating: ws (workspace_bytes(),
   // 256-byte aligned, device) and stage (n() descriptors, pinned host, not
   // reused by the caller before this batch's work has been consumed).
-  void bind_external(char* ws, InstDesc* stage) {
+  // Optional side streams (caller-owned) let such a batch run its smaller
+  // launches beside the largest one, as a batch with its own streams does.
+  void bind_external(char* ws, InstDesc* stage, hipStream_t side0 = nullptr, hipStream_t side1 = nullptr) {
     ext_ws_ = ws;
     ext_stage_ = stage;
+    ext_side_[0] = side0;
+    ext_side_[1] = side1;
   }
+  // Instance j reads its thresholds at x[j] (n() device pointers) instead of a
+  // slice of one buffer: requests of the serving loop, each with its own.
+  void set_x_ptrs(std::vector<const double*> x) { x_ptrs_ = std::move(x); }
   const int64_t* device_bad_terms() const { return d_bad_; }
   int n() const { return (int)plans_.size(); }
   const std::vector<vecchia_qmc>& qmcs() const { return qmcs_; }
@@ -145,6 +152,9 @@ class Batch {
 
   char* ext_ws_ = nullptr;
   InstDesc* ext_stage_ = nullptr;
+  hipStream_t ext_side_[kSideStreams] = {};
+  bool own_side_ = false;
+  std::vector<const double*> x_ptrs_;
   bool tables_uploaded_ = false;
   bool shared_x_ = false;
   std::vector<int64_t> x_off_;
