@@ -4,16 +4,17 @@
 //
 //   1. full_cov_build: the dense D x D covariance (plan order, FP64) and b = x / scale;
 //   2. blocked right-looking Cholesky, block 32: chol_diag (one wave, LDS),
-//      chol_panel (one thread per row below the block), chol_update (16 x 16
-//      tiles of the trailing lower triangle);
+//      chol_panel (one thread per row below the block), chol_update (64 x 64
+//      tiles of the trailing lower triangle on the FP64 matrix cores);
 //   3. chol_mirror copies L into the upper triangle (L^T), so that a column of L
 //      is contiguous;
-//   4. full_sov: one thread per lattice point, one workgroup per 256 points of
-//      one shift. Dimensions advance in blocks of 16: the block's partial sums
-//      b_a - sum_{c<j0} L_ac y_c come from the earlier y (read back from HBM,
-//      coalesced, each load feeding 16 FMAs) against the column L[j0.., c] read
-//      through the scalar cache (uniform across the workgroup); inside the block
-//      the recursion runs in registers:
+//   4. full_sov: one workgroup per 16 to 64 consecutive lattice points of one
+//      shift (16 per wave) for the whole chain; dimensions advance in blocks of
+//      64. The part of each block's limits that comes from earlier dimensions,
+//      b_a - sum_{c<j0} L_ac y_c, is a product of 64 rows of L by the earlier y
+//      of the workgroup's points, run on the FP64 matrix cores
+//      (v_mfma_f64_16x16x4); the block's own recursion then runs from LDS, one
+//      lane per point:
 //          e_a = Phi(t_a), log prod += log Phi(t_a), y_a = Phi^-1(max(w_a e_a, DBL_MIN)).
 //      Each workgroup leaves {max, sum exp(. - max)} of its points' log products;
 //   5. full_final: per shift l_r = log mean over points, then
@@ -35,8 +36,13 @@ namespace vecchia {
 namespace {
 
 constexpr int kCholB = 32;     // Cholesky block
-constexpr int kSovB = 32;      // SOV dimension block (registers)
-constexpr int kSovThreads = 256;
+constexpr int kFsB = 64;       // SOV dimension block
+constexpr int kFsWavePts = 16; // lattice points per wave (one MFMA column tile)
+
+// v_mfma_f64_16x16x4f64, D = A B + C with A 16 x 4, B 4 x 16: lane l supplies
+// A[l % 16][l / 16] and B[l / 16][l % 16], and holds D[4 e + l / 16][l % 16] in
+// element e of its four-double result (checked on gfx950).
+typedef double fs_d4 __attribute__((ext_vector_type(4)));
 
 struct CovArgs {
   const double* xs;
@@ -123,25 +129,52 @@ __global__ __launch_bounds__(256) void chol_panel(double* __restrict__ A, int64_
 }
 
 // Trailing update of the lower triangle: A[i][j] -= sum_c L[i][k0+c] L[j][k0+c]
-// for k0 + n <= j <= i (16 x 16 tiles; tiles above the diagonal exit).
+// for k0 + n <= j <= i, in 64 x 64 tiles (tiles above the diagonal exit). The
+// tile's two panels are staged in LDS column-major (Pt[c][row], zero past the
+// panel or the matrix), and each of the four waves takes a 32 x 32 quarter as
+// 2 x 2 tiles of v_mfma_f64_16x16x4 over the panel's kCholB columns.
 __global__ __launch_bounds__(256) void chol_update(double* __restrict__ A, int64_t D, int64_t k0, int n) {
   const int64_t base = k0 + n;
   const int64_t ti = blockIdx.y, tj = blockIdx.x;
   if (tj > ti) return;
-  __shared__ double Pi[16][kCholB + 1], Pj[16][kCholB + 1];
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  for (int idx = threadIdx.x; idx < 16 * n; idx += 256) {
-    const int r = idx / n, c = idx - r * n;
-    const int64_t ri = base + ti * 16 + r, rj = base + tj * 16 + r;
-    Pi[r][c] = ri < D ? A[ri * D + k0 + c] : 0.0;
-    Pj[r][c] = rj < D ? A[rj * D + k0 + c] : 0.0;
+  __shared__ double Pi[kCholB][64 + 1], Pj[kCholB][64 + 1];
+  for (int idx = threadIdx.x; idx < 64 * kCholB; idx += 256) {
+    const int r = idx / kCholB, c = idx - r * kCholB;
+    const int64_t ri = base + ti * 64 + r, rj = base + tj * 64 + r;
+    Pi[c][r] = (c < n && ri < D) ? A[ri * D + k0 + c] : 0.0;
+    Pj[c][r] = (c < n && rj < D) ? A[rj * D + k0 + c] : 0.0;
   }
   __syncthreads();
-  const int64_t i = base + ti * 16 + ty, j = base + tj * 16 + tx;
-  if (i >= D || j > i) return;
-  double s = 0.0;
-  for (int c = 0; c < n; ++c) s += Pi[ty][c] * Pj[tx][c];
-  A[i * D + j] -= s;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int wi = wv >> 1, wj = wv & 1;
+  const int m = lane & 15, kq = lane >> 4;
+  fs_d4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = fs_d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int ks = 0; ks < kCholB / 4; ++ks) {
+    const int c = 4 * ks + kq;
+    const double a0 = Pi[c][32 * wi + m], a1 = Pi[c][32 * wi + 16 + m];
+    const double b0 = Pj[c][32 * wj + m], b1 = Pj[c][32 * wj + 16 + m];
+    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+    acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+  }
+  // acc[a][b] element e (the MFMA's output layout): row 32 wi + 16 a + 4 e + kq,
+  // column 32 wj + 16 b + m of the tile
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t i = base + ti * 64 + 32 * wi + 16 * a + 4 * e + kq;
+        const int64_t j = base + tj * 64 + 32 * wj + 16 * b + m;
+        if (i < D && j <= i) A[i * D + j] -= acc[a][b][e];
+      }
 }
 
 // Upper triangle := L^T (A[j][i] = A[i][j] for j < i), 32 x 32 tiles through LDS.
@@ -166,100 +199,146 @@ __device__ __forceinline__ double log_ncdf(double t) {
                  : log1p(-0.5 * erfc(t * 0.70710678118654752440));
 }
 
-// The FP64 quantile stays out of line: inlined, it takes full_sov to the full
-// register file with spills.
+// The FP64 quantile stays out of line: inlined, it takes the recursion to the
+// full register file with spills.
 __device__ __forceinline__ double ncdf_full(double t) { return normcdf(t); }
 __device__ __noinline__ double ncdfinv_full(double u) { return normcdfinv(u); }
 
 // L: D x D with L in the lower triangle and L^T in the upper; b: D limits;
 // Z: D - 1 generators; Y: (D - 1) x S (S = N R), the y of every point,
-// dimension-major; part: R x gridDim.x partial {max, sum exp}. Separate
-// restrict-qualified arguments let the uniform column reads of L go through
-// the scalar cache.
+// dimension-major; part: R x gridDim.x partial {max, sum exp}.
 struct SovSizes {
   int64_t D, N, S;
   uint64_t seed;
 };
 
-__global__ __launch_bounds__(kSovThreads) void full_sov(const double* __restrict__ L, const double* __restrict__ bl,
-                                                        const uint64_t* __restrict__ Zt, double* __restrict__ Y,
-                                                        double2* __restrict__ part, SovSizes a) {
-  __shared__ double Ld[2 * kSovB][kSovB + 1];   // the block's own rows, then zeros
-  __shared__ double red_m[kSovThreads / 64], red_s[kSovThreads / 64];
+// Each wave owns 16 consecutive lattice points of one shift (blockIdx.y) for the
+// whole chain, and a workgroup holds NW such waves; dimensions advance in
+// blocks of kFsB. A wave depends only on its own points' y:
+//  * Earlier dimensions: T[q][p] = b_{j0+q} - sum_{c<j0} L[j0+q][c] y_c[p] is a
+//    (kFsB x j0) by (j0 x 16) product, taken as four 16 x 16 tiles of
+//    v_mfma_f64_16x16x4: the A operand is L[j0 + 16 i + m][c0 + k] (row c0 + k
+//    of the mirrored upper triangle, 16 consecutive doubles per k), the B
+//    operand y_{c0 + k} of the wave's 16 points (16 consecutive doubles of Y);
+//    four MFMAs per step of 4, the next step's loads issued before them.
+//  * The block itself: T goes to the wave's LDS slice and the wave runs the
+//    recursion right-looking over the block's rows (the block's triangle of L
+//    staged in LDS once per workgroup); lane group g = lane / 16 updates the
+//    rows q' = q + 1 + g, q + 5 + g, ... of the wave's 16 points:
+//        e = Phi(t_q), log prod += log Phi(t_q), y_q = Phi^-1(max(w_q e, DBL_MIN)),
+//        T[q'] -= L[j0 + q'][j0 + q] y_q for q' > q.
+// Two workgroup barriers per block guard the shared triangle; the wave's own y
+// (global) and T (LDS) need only its own ordering.
+template <int NW>
+__global__ __launch_bounds__(64 * NW) void full_sov(const double* __restrict__ L, const double* __restrict__ bl,
+                                                    const uint64_t* __restrict__ Zt, double* __restrict__ Y,
+                                                    double2* __restrict__ part, SovSizes a) {
+  __shared__ double T[NW][kFsB][kFsWavePts + 1];
+  __shared__ double Lb[kFsB * (kFsB + 1) / 2];   // the block's lower triangle, packed by rows
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int r = blockIdx.y;
-  const int64_t p = (int64_t)blockIdx.x * kSovThreads + threadIdx.x;   // point p + 1
-  const bool live = p < a.N;
-  const int64_t s = (int64_t)r * a.N + (live ? p : 0);
-  const int64_t D = a.D;
-  double lp = 0.0, e = 0.0;
-  for (int64_t j0 = 0; j0 < D; j0 += kSovB) {
-    const int nb = (int)(D - j0 < kSovB ? D - j0 : kSovB);
-    double acc[kSovB];
+  const int64_t D = a.D, S = a.S, N = a.N;
+  // this lane's point (column m of the wave's tile) and step offset / update group kq
+  const int m = lane & 15, kq = lane >> 4;
+  const int64_t pt = (int64_t)(blockIdx.x * NW + wv) * kFsWavePts + m;
+  const bool live = pt < N;
+  const int64_t pc = live ? pt : N - 1;   // past the shift's last point: any point of it (results unused)
+  const int64_t s_own = (int64_t)r * N + pc;
+  const double* __restrict__ yB = Y + s_own + (int64_t)kq * S;
+  double (*Tw)[kFsWavePts + 1] = T[wv];
+  double lp = 0.0;
+  for (int64_t j0 = 0; j0 < D; j0 += kFsB) {
+    const int nb = (int)(D - j0 < kFsB ? D - j0 : kFsB);
+    fs_d4 acc[4];
 #pragma unroll
-    for (int q = 0; q < kSovB; ++q) acc[q] = q < nb ? bl[j0 + q] : 0.0;
-    // earlier dimensions: acc_q -= sum_{c < j0} L[j0 + q][c] y_c, the column
-    // L[j0.., c] being row c of the mirrored upper triangle (c < j0 <= j0 + q).
-    // All kSovB entries are read (wide scalar loads); in a last, ragged block
-    // the ones past the row end fall in row c + 1 or in the limits that follow A
-    // in the workspace, and only feed acc entries that are never used.
-    const double* __restrict__ Lu = L + j0;
-#pragma unroll 2
-    for (int64_t c = 0; c < j0; ++c) {
-      // streamed past the caches: each y is read once per block
-      const double yc = __builtin_nontemporal_load(&Y[c * a.S + s]);
-      const double* __restrict__ col = Lu + c * D;
+    for (int i = 0; i < 4; ++i) acc[i] = fs_d4{0.0, 0.0, 0.0, 0.0};
+    // rows past D in a last, ragged block read other entries of L (in the array
+    // while j0 > 0, since then D > kFsB); their sums are never used
+    const double* __restrict__ aA = L + j0 + m + (int64_t)kq * D;
+    // j0 is a multiple of kFsB: whole steps of 4 earlier dimensions; the loads of
+    // step c0 + 4 are issued before the MFMAs of step c0 (two register sets)
+    const int steps = (int)(j0 / 4);
+    double av[2][4], bv[2];
+    auto load_step = [&](int st, int buf) {
+      const int64_t c0 = (int64_t)st * 4;
+      bv[buf] = __builtin_nontemporal_load(yB + c0 * S);
+      const double* __restrict__ ar = aA + c0 * D;
 #pragma unroll
-      for (int q = 0; q < kSovB; ++q) acc[q] -= col[q] * yc;
+      for (int i = 0; i < 4; ++i) av[buf][i] = ar[16 * i];
+    };
+    auto mfma_step = [&](int buf) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[buf][i], bv[buf], acc[i], 0, 0, 0);
+    };
+    if (steps > 0) load_step(0, 0);
+    int st = 0;
+    for (; st + 2 <= steps; st += 2) {
+      load_step(st + 1, 1);
+      mfma_step(0);
+      if (st + 2 < steps) load_step(st + 2, 0);
+      mfma_step(1);
     }
-    // the block's own rows, zero past its end, so that row q + 1 + i below is
-    // always in the array
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < 2 * kSovB * kSovB; idx += kSovThreads) {
-      const int q = idx / kSovB, c = idx - q * kSovB;
-      Ld[q][c] = (q < nb && c <= q) ? L[(j0 + q) * D + j0 + c] : 0.0;
+    if (st < steps) mfma_step(0);
+    // acc[i] element e (the MFMA's output layout): row 16 i + 4 e + kq of the
+    // block, point m of the wave's tile
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int q = 16 * i + 4 * e + kq;
+        Tw[q][m] = (q < nb ? bl[j0 + q] : 0.0) - acc[i][e];
+      }
+    }
+    __syncthreads();   // every wave is done with the previous block's triangle
+    for (int idx = tid; idx < kFsB * (kFsB + 1) / 2; idx += 64 * NW) {
+      int q = (int)((__builtin_sqrt(8.0 * idx + 1.0) - 1.0) * 0.5);
+      while (q * (q + 1) / 2 > idx) --q;
+      while ((q + 1) * (q + 2) / 2 <= idx) ++q;
+      const int c = idx - q * (q + 1) / 2;
+      Lb[idx] = q < nb ? L[(j0 + q) * D + j0 + c] : 0.0;
     }
     __syncthreads();
-    // The recursion inside the block, right-looking: acc[0] always holds the
-    // current dimension's (b - sum L y); once its y is drawn, the later entries
-    // take their term in it and move down one place. The loop is not unrolled,
-    // so the Phi and Phi^-1 code is inlined once and acc stays in registers.
 #pragma unroll 1
     for (int q = 0; q < nb; ++q) {
-      const double t = acc[0] / Ld[q][q];
-      e = ncdf_full(t);
+      // every lane group evaluates the same point's factor; group 0 keeps it
+      const double t = Tw[q][m] / Lb[q * (q + 1) / 2 + q];
+      const double e = ncdf_full(t);
       lp += log_ncdf(t);
       const int64_t dim = j0 + q;
-      double y = 0.0;
       if (dim < D - 1) {
-        const uint64_t S = splitmix64(a.seed, (1ULL << 63) | ((uint64_t)r << 32) | (uint64_t)dim);
-        const uint64_t U = (uint64_t)(p + 1) * Zt[dim] + S;
+        const uint64_t Sh = splitmix64(a.seed, (1ULL << 63) | ((uint64_t)r << 32) | (uint64_t)dim);
+        const uint64_t U = (uint64_t)(pc + 1) * Zt[dim] + Sh;
         const double w = lattice_coord_f64(U);
-        y = ncdfinv_full(fmax(w * e, 2.2250738585072014e-308));
-        if (live) Y[dim * a.S + s] = y;
+        const double y = ncdfinv_full(fmax(w * e, 2.2250738585072014e-308));
+        if (kq == 0 && live) Y[dim * S + s_own] = y;
+#pragma unroll 2
+        for (int q2 = q + 1 + kq; q2 < nb; q2 += 4) Tw[q2][m] -= Lb[q2 * (q2 + 1) / 2 + q] * y;
       }
-#pragma unroll
-      for (int i = 0; i + 1 < kSovB; ++i) acc[i] = acc[i + 1] - Ld[q + 1 + i][q] * y;
     }
+    // the wave's own y stores are read back by its next product (other lanes)
+    __threadfence_block();
   }
-  // workgroup {max, sum exp(lp - max)} over its live points
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  double m = live ? lp : -HUGE_VAL;
+  // the wave's {max, sum exp(lp - max)} over its live points (lane group 0)
+  const bool own = live && kq == 0;
+  double mx = own ? lp : -HUGE_VAL;
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
-  if (lane == 0) red_m[wv] = m;
-  __syncthreads();
-  double M = red_m[0];
-  for (int k = 1; k < kSovThreads / 64; ++k) M = fmax(M, red_m[k]);
-  double x = (live && M > -HUGE_VAL) ? exp(lp - M) : 0.0;
+  for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+  double x = (own && mx > -HUGE_VAL) ? exp(lp - mx) : 0.0;
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-  if (lane == 0) red_s[wv] = x;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double sum = 0.0;
-    for (int k = 0; k < kSovThreads / 64; ++k) sum += red_s[k];
-    part[(int64_t)r * gridDim.x + blockIdx.x] = make_double2(M, sum);
+  if (lane == 0) part[((int64_t)r * gridDim.x + blockIdx.x) * NW + wv] = make_double2(mx, x);
+}
+
+// Waves per workgroup (16 points each) for N points per shift and R shifts: four
+// (one wave on each SIMD of a compute unit, sharing the workgroup's loads of L)
+// unless that leaves compute units without a workgroup; then the most that
+// still give every compute unit one.
+int full_sov_waves(int64_t N, int64_t R, int n_cu) {
+  for (int nw = 4; nw > 1; --nw) {
+    const int64_t P = (int64_t)kFsWavePts * nw;
+    if ((N + P - 1) / P * R >= n_cu) return nw;
   }
+  return 1;
 }
 
 // log of the mean over points of shift r, from its workgroup partials (in order)
@@ -323,7 +402,8 @@ extern "C" vecchia_status vecchia_full_logcdf(vecchia_plan_t plan, const double*
   // workspace: A (D x D), b (D), Y ((D-1) x S), then the partials at a 16-byte offset
   const int64_t n_head = D * D + D + std::max<int64_t>(1, D - 1) * S;
   const int64_t n_head_even = n_head + (n_head & 1);
-  const double bytes = 8.0 * (double)n_head_even + 16.0 * R * ((N + kSovThreads - 1) / kSovThreads);
+  // partials: one per wave, at most ceil(N / 16) + 3 per shift (the last workgroup of a shift)
+  const double bytes = 8.0 * (double)n_head_even + 16.0 * R * ((N + kFsWavePts - 1) / kFsWavePts + 3);
   if (D > 40000 || bytes > 64e9)
     return set_error(VECCHIA_E_INVALID, "the full-dimension estimator needs D <= 40000 and at most 64 GB of workspace");
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
@@ -363,7 +443,7 @@ extern "C" vecchia_status vecchia_full_logcdf(vecchia_plan_t plan, const double*
     if (e == hipSuccess && rest > 0) {
       hipLaunchKernelGGL(chol_panel, dim3((unsigned)((rest + 255) / 256)), dim3(256), 0, s, A, D, k0, n);
       e = hipGetLastError();
-      const unsigned t = (unsigned)((rest + 15) / 16);   // 16 x 16 tiles of the trailing triangle
+      const unsigned t = (unsigned)((rest + 63) / 64);   // 64 x 64 tiles of the trailing triangle
       if (e == hipSuccess) {
         hipLaunchKernelGGL(chol_update, dim3(t, t), dim3(256), 0, s, A, D, k0, n);
         e = hipGetLastError();
@@ -375,14 +455,23 @@ extern "C" vecchia_status vecchia_full_logcdf(vecchia_plan_t plan, const double*
     hipLaunchKernelGGL(chol_mirror, dim3(t32, t32), dim3(256), 0, s, A, D);
     e = hipGetLastError();
   }
-  const unsigned nblk = (unsigned)((N + kSovThreads - 1) / kSovThreads);
+  hipDeviceProp_t prop{};
+  int n_cu = 256;
+  if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0) n_cu = prop.multiProcessorCount;
+  const int nw = full_sov_waves(N, R, n_cu);
+  const int64_t P = (int64_t)kFsWavePts * nw;
+  const unsigned nblk = (unsigned)((N + P - 1) / P);
   if (e == hipSuccess) {
     SovSizes sz{D, N, S, q->seed};
-    hipLaunchKernelGGL(full_sov, dim3(nblk, (unsigned)R), dim3(kSovThreads), 0, s, A, b, Zt, Y, part, sz);
+    const dim3 grid(nblk, (unsigned)R), block(64 * nw);
+    if (nw == 4) hipLaunchKernelGGL(full_sov<4>, grid, block, 0, s, A, b, Zt, Y, part, sz);
+    else if (nw == 3) hipLaunchKernelGGL(full_sov<3>, grid, block, 0, s, A, b, Zt, Y, part, sz);
+    else if (nw == 2) hipLaunchKernelGGL(full_sov<2>, grid, block, 0, s, A, b, Zt, Y, part, sz);
+    else hipLaunchKernelGGL(full_sov<1>, grid, block, 0, s, A, b, Zt, Y, part, sz);
     e = hipGetLastError();
   }
   if (e == hipSuccess) {
-    hipLaunchKernelGGL(full_final, dim3(1), dim3(64), 0, s, part, (int)nblk, (int)R, N, out_dev);
+    hipLaunchKernelGGL(full_final, dim3(1), dim3(64), 0, s, part, (int)nblk * nw, (int)R, N, out_dev);
     e = hipGetLastError();
   }
   if (e != hipSuccess) return hip_error(e, "full-dimension launch");

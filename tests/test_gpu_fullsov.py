@@ -25,8 +25,8 @@ def _full(V, torch, plan, x_np, q, scale=1.0, cov=None):
 
 @pytest.mark.parametrize("D,N,R", [(1, 64, 2), (7, 300, 4), (60, 1000, 4), (203, 700, 3)])
 def test_fp64_full_matches_the_oracle(D, N, R):
-    # several dimension blocks (16) and Cholesky blocks (32) with ragged ends,
-    # point counts that are not multiples of the 256-point workgroup
+    # several dimension blocks (64) and Cholesky blocks (32) with ragged ends,
+    # point counts that are not multiples of the 16-point wave tile
     torch = torch_cuda()
     from paper_2007_15195_amd import vecchia as V
     inst = W.small_random_instance(D, 5, 500 + D, ordering=W.ORDER_MAXMIN, n_points=N, n_shifts=R)
