@@ -26,8 +26,9 @@ baseline on a bounded sample, and one object per further workload:
               FP64 on the same plan, 10^4 x 10 points;
   c5_serving  mixed requests (D in [1000, 100000], m in 5..30, per-request
               range and scale factor, 2048-8192 x 8 points) through the serving
-              loop: capacity with every request queued at once, then Poisson
-              arrivals at 80 % of it with p50/p99 latency;
+              loop after 50 warm-up requests: capacity with 1000 requests
+              queued at once, then the same requests as Poisson arrivals at
+              50, 80 and 95 % of it with p50/p99 latency (16 GB budget);
   scale_mixture  the scale-mixture CDF E Phi_D(x / R), R Pareto(2), on the headline
               geometry (24 search evaluations at 1/16 size + 48 nodes per call);
   censored_likelihood  the censored log-likelihood of Section 4 over 1006 weekly
@@ -57,18 +58,66 @@ sys.path.insert(0, ROOT)
 
 # Dominant kernel figures used by the roofline (qmc_f32<10>, gfx950 build):
 # VALU instructions per SOV step counted on the main path of the kernel's
-# unrolled chain in its assembly (482 per 10-step chain, rare branches not
-# taken); updated whenever the kernel changes.
+# unrolled chain in its assembly (rare branches not taken); cross-checked on
+# every run against SQ_INSTS_VALU x 64 / steps of the committed counter profile
+# (within 2 %, the difference being each work item's set-up).
 SLOTS_PER_STEP_F32_K10 = 48.2
 # MI355X FP32 vector peak 157.3 TFLOP/s = 256 CUs x 2.4 GHz x 128 FMA lanes x 2:
-# 78.64e12 full-rate VALU lane-slots per second.
+# 78.64e12 full-rate VALU lane-slots per second. FP64 vector peak 78.6 TFLOP/s.
 VALU_PEAK_TSLOTS = 256 * 2.4e9 * 128 / 1e12
+FP32_PEAK_TFLOPS = 157.3
+FP64_PEAK_TFLOPS = 78.6
 # Transcendental instructions per SOV step on that path (the rest are full-rate):
 # Phi^-1 takes a log2, a sqrt and a reciprocal, Phi a reciprocal and an exp2.
 TRANS_PER_STEP = {"exp": 1, "log": 1, "rcp": 2, "sqrt": 1}
-# HBM bytes per launch of qmc_f32<10> from rocprofv3 FETCH_SIZE x 2.0 +
-# WRITE_SIZE x 1.0 (factors from a 256 MiB copy); None once the kernel changes.
-TRAFFIC_BYTES_F32_K10 = 12.28e6    # (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000) per launch, profiles/qmc_f32_k10_uniform2500_pmc.md
+# rocprofv3 counter summaries of the QMC kernels at the headline workload; each
+# holds a `counters_json:` line with per-dispatch counters and the hash of the
+# kernel sources it was taken on (a changed kernel makes its figures stale).
+PMC_F32 = os.path.join(ROOT, "profiles", "qmc_f32_k10_uniform2500_pmc.md")
+PMC_F64 = os.path.join(ROOT, "profiles", "qmc_f64_k10_uniform2500_pmc.md")
+KERNEL_SOURCES = ["kernels_qmc.hip", "device_math_f32.h", "lattice.h", "fp32_math_coeffs.h", "vecchia_internal.h"]
+
+
+def kernel_source_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2007_15195_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_counters(path):
+    """The `counters_json:` line of a committed counter summary, or None."""
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("counters_json:"):
+                return json.loads(line[len("counters_json:"):])
+    return None
+
+
+def counter_figures(c, sha, avg_launch_s, steps_per_launch, peak_tflops, prec):
+    """Per-step instruction and FLOP figures of a counter profile, and the FLOP
+    rate they give at the live launch time: FMA = 2 flops, ADD / MUL and a
+    transcendental 1 flop each, per lane (x 64)."""
+    if c is None:
+        return {"status": "missing"}
+    k = c["counters"]
+    st = float(c["sov_steps_per_dispatch"])
+    sfx = "F32" if prec == 32 else "F64"
+    flops = 64.0 * (2.0 * k[f"SQ_INSTS_VALU_FMA_{sfx}"] + k[f"SQ_INSTS_VALU_ADD_{sfx}"] +
+                    k[f"SQ_INSTS_VALU_MUL_{sfx}"] + k[f"SQ_INSTS_VALU_TRANS_{sfx}"])
+    fps = flops / st
+    achieved = fps * steps_per_launch / avg_launch_s / 1e12
+    out = {"status": "current" if c.get("source_sha") == sha else "stale (kernel changed since)",
+           "source_sha": c.get("source_sha"), "valu_slots_per_step": 64.0 * k["SQ_INSTS_VALU"] / st,
+           "flops_per_step": fps, "achieved_tflops": achieved, "peak_tflops": peak_tflops,
+           "frac": achieved / peak_tflops}
+    if "FETCH_SIZE" in k and "WRITE_SIZE" in k:
+        out["traffic_bytes"] = 1024.0 * (k["FETCH_SIZE"] * c["fetch_factor"] + k["WRITE_SIZE"] * c["write_factor"])
+    return out
 
 
 def parse():
@@ -83,11 +132,15 @@ def parse():
     ap.add_argument("--cpu-terms", type=int, default=500)
     ap.add_argument("--fp32-only", action="store_true",
                     help="time the full FP32 step only (short runs under a profiler)")
+    ap.add_argument("--fp64-only", action="store_true",
+                    help="time the plain FP64 log-CDF only (short runs under a profiler)")
     ap.add_argument("--censored-T", type=int, default=1006)
     ap.add_argument("--comparator-grids", type=lambda v: [int(t) for t in v.split(",")], default=[15, 30, 50, 75, 100])
     ap.add_argument("--sections", default="c1,c2,c3,c4,c5,mix,cens,full",
                     help="comma list of workloads to run besides the headline (c2 is always run)")
-    ap.add_argument("--serving-requests", type=int, default=200)
+    ap.add_argument("--serving-requests", type=int, default=1000)
+    ap.add_argument("--sections-only", action="store_true",
+                    help="run only the listed sections and print their objects (for profiling runs)")
     ap.add_argument("--no-autotune", action="store_true")
     return ap.parse_args()
 
@@ -124,10 +177,47 @@ def cpu_baseline(inst, n_terms):
                   terms_subset=sub1, plan_cache=(perm, nbrs), processes=1)
     t_one = time.perf_counter() - t0
     return {"value": inst.D / t_full, "unit": "terms/s", "cores": procs, "kind": "oracle",
+            "os_cpu_count": os.cpu_count(), "affinity_cpus": len(os.sched_getaffinity(0)),
             "sample": f"plan of all {inst.D} locations ({t_plan:.2f} s) + {len(sub)} of {inst.D} "
                       f"terms ({t_terms:.2f} s on {procs} processes), extrapolated to all terms",
             "single_core": {"value": inst.D / (t_plan + t_one * inst.D / len(sub1)), "unit": "terms/s",
                             "sample": f"the same plan + {len(sub1)} terms ({t_one:.2f} s) in one process"}}
+
+
+def cpu_baseline_subset(V, insts, plans, total_terms, n_inst, n_terms, seed):
+    """The oracle on a seeded subset of a large workload: n_inst instances (every
+    instance when there are fewer), each with its k < m terms and n_terms seeded
+    others, on the plan's own ordering and neighbour lists (read back from the GPU
+    plan, whose sets the tests hold equal to the oracle's: the oracle's exact
+    O(D^2) maxmin alone would take minutes at these sizes). Terms/s on the sample,
+    extrapolated to all terms of the workload by its mean cost per term."""
+    import oracle
+    rng = np.random.default_rng(abs(hash(seed)) % (2 ** 32))
+    pick = sorted(rng.choice(len(insts), size=min(n_inst, len(insts)), replace=False).tolist())
+    procs = oracle.vecchia.default_processes()
+    t_terms, n_done, steps_done = 0.0, 0, 0.0
+    for j in pick:
+        inst, plan = insts[j], plans[j]
+        perm, nbr = V.vecchia_plan_neighbours(plan)
+        nbrs = [np.array([v for v in row if v >= 0], dtype=np.int64) for row in nbr]
+        head = list(range(min(inst.m + 1, inst.D)))
+        rest = rng.choice(np.arange(len(head), inst.D), size=min(n_terms, inst.D - len(head)), replace=False)
+        sub = sorted(set(head) | set(int(v) for v in rest))
+        c = inst.cov
+        t0 = time.perf_counter()
+        oracle.logcdf(inst.locs, inst.x, inst.m, c.family, c.nu, c.sigma2, c.range, c.nugget, inst.ordering,
+                      inst.qmc.n_points, inst.qmc.n_shifts, inst.qmc.seed, terms_subset=sub,
+                      plan_cache=(perm.astype(np.int64), nbrs), processes=procs)
+        t_terms += time.perf_counter() - t0
+        n_done += len(sub)
+        steps_done += inst.qmc.n_points * inst.qmc.n_shifts * sum(min(i, inst.m) for i in sub)
+    all_steps = sum(i.qmc.n_points * i.qmc.n_shifts * (i.m * (i.D - i.m) + i.m * (i.m - 1) // 2) for i in insts)
+    steps_per_s = steps_done / t_terms
+    return {"value": total_terms / (all_steps / steps_per_s), "unit": "terms/s (extrapolated)", "cores": procs,
+            "kind": "oracle", "os_cpu_count": os.cpu_count(), "affinity_cpus": len(os.sched_getaffinity(0)),
+            "sov_steps_per_s": steps_per_s,
+            "sample": f"{n_done} terms of {len(pick)} instance(s) ({t_terms:.1f} s on {procs} processes; "
+                      f"plans read back from the GPU), extrapolated by SOV steps to all {total_terms} terms"}
 
 
 def autotune(V, n_points, n_shifts, ms, sp):
@@ -240,7 +330,24 @@ def bench_comparator(V, torch, args):
                     row[f"vecchia_m{m}_{name}"] = {"seconds": sec, "logF": float(o[0]), "se": float(o[1])}
                 V.vecchia_plan_destroy(p)
             rows.append(row)
-    return {"workload": "exp_grids_unit_spacing_comparator", "n_points": N, "n_shifts": R, "rows": rows}
+    # compact rows: seconds and log F of the full-dimension estimate and of the
+    # Vecchia log-CDF at each m (FP32 / FP64)
+    table = []
+    for row in rows:
+        t = {"grid": row["grid"], "range": row["range"],
+             "full": [round(row["full_sov_fp64"]["seconds"], 4), round(row["full_sov_fp64"]["logF"], 3),
+                      round(row["full_sov_fp64"]["se"], 3)]}
+        for mm in (5, 10, 30, 50):
+            a, b = row[f"vecchia_m{mm}_fp32"], row[f"vecchia_m{mm}_fp64"]
+            t[f"m{mm}"] = [round(a["seconds"], 4), round(b["seconds"], 4), round(a["logF"], 3)]
+        table.append(t)
+    big = [r for r in rows if r["D"] == 10_000]
+    summary = {}
+    if big:
+        summary = {"full_sov_seconds_100x100": [r["full_sov_fp64"]["seconds"] for r in big],
+                   "vecchia_m30_fp32_seconds_100x100": [r["vecchia_m30_fp32"]["seconds"] for r in big]}
+    return {"workload": "exp_grids_unit_spacing_comparator", "n_points": N, "n_shifts": R,
+            "columns": "full: [s, logF, se]; mK: [fp32 s, fp64 s, fp32 logF]", "rows": table, **summary}
 
 
 # Section 4.1 / Table 1: range, rotation angle, aspect ratio and mixing law
@@ -364,8 +471,10 @@ def bench_c3(V, torch, args):
     rel = np.abs(o32[:, 0] - o64[:, 0]) / np.abs(o64[:, 0])
     res["fp32_vs_fp64_rel_total"] = {"max": float(rel.max()), "median": float(np.median(rel))}
     res["fp32_speedup"] = res["fp64"]["ms"] / res["fp32"]["ms"]
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline_subset(V, insts, plans, terms, 12, 150, "c3")
     if tuned is not None:
-        res["autotune"] = tuned
+        res["autotune_chunk_points"] = {"fp32": tuned["chunk_points_fp32"], "fp64": tuned["chunk_points_fp64"]}
     for p in plans:
         V.vecchia_plan_destroy(p)
     return res
@@ -397,6 +506,8 @@ def bench_c4(V, torch, args):
         res[name] = {"ms": 1e3 * sec, "terms_per_s": D / sec, "samples_per_s": D * N * R / sec,
                      "sov_steps_per_s": steps / sec, "logF": float(got[name][0][0]), "se": float(got[name][0][1])}
     res["fp32_speedup"] = res["fp64"]["ms"] / res["fp32"]["ms"]
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline_subset(V, [inst], [plan], D, 1, 1200, "c4")
     d = np.abs(got["fp32"][1] - got["fp64"][1])
     nz = got["fp64"][1] != 0.0          # log-terms that round to 0 in FP64 have no relative error
     res["fp32_vs_fp64"] = {"rel_total": abs(got["fp32"][0][0] - got["fp64"][0][0]) / abs(got["fp64"][0][0]),
@@ -404,7 +515,7 @@ def bench_c4(V, torch, args):
                            "max_rel_term": float(np.max(d[nz] / np.abs(got["fp64"][1][nz]))),
                            "terms_rounding_to_zero": int(np.sum(~nz))}
     if tuned is not None:
-        res["autotune"] = tuned
+        res["autotune_chunk_points"] = {"fp32": tuned["chunk_points_fp32"], "fp64": tuned["chunk_points_fp64"]}
     V.vecchia_plan_destroy(plan)
     return res
 
@@ -432,35 +543,46 @@ def _serve(V, srv, plans, reqs, xs, arrivals):
 
 
 def bench_c5(V, torch, args):
-    """Serving loop: capacity, then Poisson arrivals at 80 % of it."""
+    """Serving loop: 50 warm-up requests, then capacity with 1000 requests queued
+    at once, then the same 1000 requests as Poisson arrivals at 50, 80 and 95 %
+    of that capacity (p50 / p99 latency per load); 16 GB HBM budget, 16 slots."""
     import workloads as W
-    st = W.serving_stream(n_requests=args.serving_requests)
+    n_warm, n_req = 50, args.serving_requests
+    st = W.serving_stream(n_requests=n_warm + n_req)
     t0 = time.perf_counter()
     plans = [V.vecchia_plan(p.locs, p.ordering, p.m, p.cov) for p in st.plans]
     t_plans = time.perf_counter() - t0
     xs = [torch.tensor(r.x, dtype=torch.float64, device="cuda") for r in st.requests]
     torch.cuda.synchronize()
-    reqs = st.requests
+    warm, reqs, xr = st.requests[:n_warm], st.requests[n_warm:], xs[n_warm:]
     terms = sum(st.plans[r.plan_id].D for r in reqs)
-    srv = V.vecchia_server_create(8 << 30, 16)
-    # warm-up: a few requests (first launches, graph-free server path)
-    _serve(V, srv, plans, reqs[:8], xs[:8], np.zeros(8))
-    wall, lat_cap = _serve(V, srv, plans, reqs, xs, np.zeros(len(reqs)))
+    samples = sum(st.plans[r.plan_id].D * r.qmc.n_points * r.qmc.n_shifts for r in reqs)
+    sov = sum(r.qmc.n_points * r.qmc.n_shifts * (st.plans[r.plan_id].m * (st.plans[r.plan_id].D - st.plans[r.plan_id].m)
+                                                  + st.plans[r.plan_id].m * (st.plans[r.plan_id].m - 1) // 2)
+              for r in reqs)
+    budget, slots = 16 << 30, 16
+    srv = V.vecchia_server_create(budget, slots)
+    _serve(V, srv, plans, warm, xs[:n_warm], np.zeros(n_warm))
+    wall, _ = _serve(V, srv, plans, reqs, xr, np.zeros(len(reqs)))
     rate = len(reqs) / wall
+    res = {"workload": "serving_stream", "plans": len(plans), "warmup_requests": n_warm, "requests": len(reqs),
+           "plan_seconds_all": t_plans, "hbm_budget_bytes": budget, "slots": slots,
+           "mean_m": float(np.mean([st.plans[r.plan_id].m for r in reqs])),
+           "capacity": {"requests_per_s": rate, "terms_per_s": terms / wall, "samples_per_s": samples / wall,
+                        "sov_steps_per_s": sov / wall}}
     arr = np.array([r.arrival_s for r in reqs])
-    arr = arr / arr[-1] * (len(reqs) / (0.8 * rate))          # same Poisson pattern at 80 % load
-    wall80, lat = _serve(V, srv, plans, reqs, xs, arr)
+    arr = arr - arr[0]
+    for load in (0.5, 0.8, 0.95):
+        a = arr / arr[-1] * (len(reqs) / (load * rate))      # the same Poisson pattern at this load
+        w, lat = _serve(V, srv, plans, reqs, xr, a)
+        res[f"poisson_{int(round(100 * load))}pct"] = {
+            "offered_requests_per_s": load * rate, "requests_per_s": len(reqs) / w, "terms_per_s": terms / w,
+            "latency_ms_p50": 1e3 * float(np.percentile(lat, 50)), "latency_ms_p99": 1e3 * float(np.percentile(lat, 99)),
+            "latency_ms_max": 1e3 * float(lat.max())}
     V.vecchia_server_destroy(srv)
     for p in plans:
         V.vecchia_plan_destroy(p)
-    return {"workload": "serving_stream", "plans": len(plans), "requests": len(reqs),
-            "plan_seconds_all": t_plans, "hbm_budget_bytes": 8 << 30, "slots": 16,
-            "capacity": {"requests_per_s": rate, "terms_per_s": terms / wall},
-            "poisson_80pct": {"offered_requests_per_s": 0.8 * rate, "requests_per_s": len(reqs) / wall80,
-                              "terms_per_s": terms / wall80,
-                              "latency_ms_p50": 1e3 * float(np.percentile(lat, 50)),
-                              "latency_ms_p99": 1e3 * float(np.percentile(lat, 99)),
-                              "latency_ms_max": 1e3 * float(lat.max())}}
+    return res
 
 
 def main():
@@ -474,6 +596,17 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.sections_only:
+        fns = {"c1": ("c1_grid", bench_c1), "c3": ("c3_batched", bench_c3), "c4": ("c4_large", bench_c4),
+               "c5": ("c5_serving", bench_c5), "mix": ("scale_mixture", bench_mixture),
+               "cens": ("censored_likelihood", bench_censored), "full": ("full_dimension_comparator", bench_comparator)}
+        res = {}
+        for sec in args.sections.split(","):
+            if sec in fns:
+                key, fn = fns[sec]
+                res[key] = fn(V, torch, args)
+                print(json.dumps({key: res[key]}), flush=True)
+        return
     inst = make_instance(args.workload)
     D, m = inst.D, inst.m
     stream = torch.cuda.Stream()
@@ -493,6 +626,20 @@ def main():
     def step(q):
         V.vecchia_replan(plan, inst.locs, inst.ordering, stream=sp)
         V.vecchia_logcdf(plan, x, q, out, stream=sp)
+
+    if args.fp64_only:
+        for _ in range(max(1, args.warmup)):
+            V.vecchia_logcdf(plan, x, q64, out, stream=sp)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            V.vecchia_logcdf(plan, x, q64, out, stream=sp)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / args.steps
+        V.vecchia_plan_destroy(plan)
+        print(json.dumps({"workload": inst.name, "fp64_ms_per_logcdf": ms, "logF": float(out.cpu().numpy()[0])}),
+              flush=True)
+        return
 
     # ---- full path, FP32 loop: warmup, then the timed region with kernel events
     for _ in range(args.warmup):
@@ -540,6 +687,15 @@ def main():
         V.vecchia_logcdf(plan, x, q64, out, stream=sp)
     torch.cuda.synchronize()
     ms_fp64 = 1e3 * (time.perf_counter() - t0) / args.fp64_steps
+    # the plain FP64 kernel's own launch time (HIP events on its stream)
+    V.vecchia_profile_reset()
+    V.vecchia_profile_enable(1)
+    for _ in range(args.fp64_steps):
+        V.vecchia_logcdf(plan, x, q64, out, stream=sp)
+    torch.cuda.synchronize()
+    V.vecchia_profile_enable(0)
+    k64_ms, k64_launches, k64_steps = V.vecchia_profile_read(m, V.VECCHIA_FP64)
+    V.vecchia_profile_reset()
     t32, t64 = terms32.cpu().numpy(), terms64.cpu().numpy()
 
     # ---- the paper-literal estimator (separate points for each term's numerator
@@ -566,6 +722,16 @@ def main():
     kernel_avg_ms = k_ms / max(k_launches, 1)
     steps_per_launch = k_steps / max(k_launches, 1)
     achieved = steps_per_launch * SLOTS_PER_STEP_F32_K10 / (kernel_avg_ms * 1e-3) / 1e12
+    sha = kernel_source_sha()
+    c32 = counter_figures(load_counters(PMC_F32), sha, kernel_avg_ms * 1e-3, steps_per_launch, FP32_PEAK_TFLOPS, 32)
+    k64_avg_ms = k64_ms / max(k64_launches, 1)
+    c64 = counter_figures(load_counters(PMC_F64), sha, k64_avg_ms * 1e-3, k64_steps / max(k64_launches, 1),
+                          FP64_PEAK_TFLOPS, 64)
+    if c32.get("status") == "current":
+        # the assembly count of the chain's main path against the executed instructions
+        c32["slots_check"] = ("ok" if abs(c32["valu_slots_per_step"] / SLOTS_PER_STEP_F32_K10 - 1.0) <= 0.02
+                              else "differs by more than 2 %")
+    traffic = c32.get("traffic_bytes") if c32.get("status") == "current" else None
     res = {
         "metric": "Vecchia terms/s (m=10; plan + log-CDF per step)",
         "value": D / (ms_per_step * 1e-3),
@@ -597,14 +763,18 @@ def main():
                                   "max_abs_term": float(np.max(np.abs(t32[:, 0] - t64[:, 0])))},
         "roofline": {"bound": "alu", "kernel": f"qmc_f32<{m}>",
                      "achieved": achieved, "peak": VALU_PEAK_TSLOTS, "unit": "T VALU-slots/s",
-                     "frac": achieved / VALU_PEAK_TSLOTS, "traffic": TRAFFIC_BYTES_F32_K10,
+                     "frac": achieved / VALU_PEAK_TSLOTS, "traffic": traffic,
                      "avg_launch_ms": kernel_avg_ms, "sov_steps_per_launch": steps_per_launch,
                      "slots_per_step": SLOTS_PER_STEP_F32_K10,
                      "measured_rates_wave_instr_per_cu_ns": {k: round(v, 4) for k, v in rates.items()},
-                     "measured_ceiling": ceiling, "frac_of_measured_ceiling": achieved / ceiling},
+                     "measured_ceiling": ceiling, "frac_of_measured_ceiling": achieved / ceiling,
+                     "fp32_flops": c32,
+                     "fp64_plain_kernel": {"kernel": f"qmc_f64<{m}>", "avg_launch_ms": k64_avg_ms,
+                                           "sov_steps_per_launch": k64_steps / max(k64_launches, 1),
+                                           "fp64_flops": c64}},
     }
     if tuned is not None:
-        res["autotune"] = tuned
+        res["autotune_chunk_points"] = [tuned["chunk_points_fp32"], tuned["chunk_points_fp64"]]
     sections = set(args.sections.split(","))
     if "c1" in sections:
         res["c1_grid"] = bench_c1(V, torch, args)
@@ -622,7 +792,56 @@ def main():
         res["full_dimension_comparator"] = bench_comparator(V, torch, args)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(inst, args.cpu_terms)
+    res["summary"] = summary(res)
     print(json.dumps(res), flush=True)
+
+
+def _r(v, k=4):
+    return float(f"{v:.{k}g}") if isinstance(v, (int, float)) and v is not None and math.isfinite(v) else v
+
+
+def summary(res):
+    """The secondary figures in a few hundred bytes, last on the line."""
+    out = {"fp64_plain_speedup": _r(res["fp64_plain"]["fp32_speedup"]),
+           "fp32_vs_fp64_rel_total": _r(res["accuracy_fp32_vs_fp64"]["rel_total"], 2),
+           "fp32_vs_fp64_max_term": _r(res["accuracy_fp32_vs_fp64"]["max_abs_term"], 2),
+           "logcdf_only_terms_per_s": _r(res["logcdf_only"]["terms_per_s"])}
+    if "c1_grid" in res:
+        c = res["c1_grid"]
+        out["c1"] = {"fp64_terms_per_s": _r(c["fp64"]["terms_per_s"]), "fp32_terms_per_s": _r(c["fp32"]["terms_per_s"])}
+    if "c3_batched" in res:
+        c = res["c3_batched"]
+        out["c3"] = {"terms_per_s": _r(c["fp32"]["terms_per_s"]), "samples_per_s": _r(c["fp32"]["samples_per_s"]),
+                     "sov_steps_per_s": _r(c["fp32"]["sov_steps_per_s"]), "fp32_speedup": _r(c["fp32_speedup"]),
+                     "max_rel_vs_fp64": _r(c["fp32_vs_fp64_rel_total"]["max"], 2)}
+        if "cpu_baseline" in c:
+            out["c3"]["cpu_terms_per_s_extrapolated"] = _r(c["cpu_baseline"]["value"])
+    if "c4_large" in res:
+        c = res["c4_large"]
+        out["c4"] = {"terms_per_s": _r(c["fp32"]["terms_per_s"]), "samples_per_s": _r(c["fp32"]["samples_per_s"]),
+                     "fp32_speedup": _r(c["fp32_speedup"]), "rel_total_vs_fp64": _r(c["fp32_vs_fp64"]["rel_total"], 2)}
+        if "cpu_baseline" in c:
+            out["c4"]["cpu_terms_per_s_extrapolated"] = _r(c["cpu_baseline"]["value"])
+    if "c5_serving" in res:
+        c = res["c5_serving"]
+        loads = [k for k in c if k.startswith("poisson_")]
+        out["c5"] = {"capacity_terms_per_s": _r(c["capacity"]["terms_per_s"]),
+                     "capacity_samples_per_s": _r(c["capacity"]["samples_per_s"]),
+                     "capacity_sov_steps_per_s": _r(c["capacity"]["sov_steps_per_s"]),
+                     "loads": [k[len("poisson_"):] for k in loads],
+                     "p50_ms": [_r(c[k]["latency_ms_p50"], 3) for k in loads],
+                     "p99_ms": [_r(c[k]["latency_ms_p99"], 3) for k in loads]}
+    if "scale_mixture" in res:
+        c = res["scale_mixture"]
+        out["mixture"] = {"fp32_ms_per_call": _r(c["fp32"]["ms_per_call"]), "fp32_speedup": _r(c["fp32_speedup"])}
+    if "censored_likelihood" in res:
+        c = res["censored_likelihood"]
+        out["censored"] = {"fp32_s_per_likelihood": _r(c["fp32"]["seconds_per_likelihood"]),
+                           "fp32_speedup_subset": _r(c["fp32_speedup_on_subset"])}
+    if "full_dimension_comparator" in res:
+        c = res["full_dimension_comparator"]
+        out["comparator_100x100"] = {k: [_r(v) for v in c[k]] for k in c if k.endswith("100x100")}
+    return out
 
 
 if __name__ == "__main__":

@@ -146,7 +146,10 @@ vecchia_status vecchia_plan(const double* locs_host, int64_t D, int32_t dim, int
                             void* hip_stream, vecchia_plan_t* out);
 
 /* Plan over an explicit D x D covariance (row-major, host, D <= 4096) with
- * identity ordering; used to run closed-form cases through the same kernels.
+ * identity ordering: the Vecchia product of Section 2.2, eq. (6), over a given
+ * Sigma instead of one built from locations (Section 2.1 writes the
+ * approximation for any covariance); used to run closed-form cases through the
+ * same kernels.
  * nbr_host: D x m row-major plan indices, each row listing its conditioning set
  * (entries < i, distinct) first, padded with -1; NULL means the min(m, i)
  * immediately preceding indices in ascending order.
@@ -274,7 +277,9 @@ vecchia_status vecchia_logcdf_noalloc(vecchia_plan_t plan, const double* x_dev, 
  * (-1 when OK) and in the error message. */
 vecchia_status vecchia_plan_status(vecchia_plan_t plan, int64_t* bad_term);
 
-/* Release a plan. BUSY if server requests on it are still in flight. */
+/* Release a plan and its device memory (the plan of Section 2.1's ordering and
+ * neighbour sets, built once and reused by every evaluation). BUSY if server
+ * requests on it are still in flight; the plan is then left intact. */
 vecchia_status vecchia_plan_destroy(vecchia_plan_t plan);
 
 /* A batch of n instances evaluated in one pass: one setup launch, one QMC
@@ -462,28 +467,40 @@ vecchia_status vecchia_probe_math(int32_t what, int64_t n, const double* in_dev,
 vecchia_status vecchia_probe_lattice(uint64_t seed, int64_t term, int32_t shift, int32_t dim, int32_t second,
                                      int64_t n, double* w64_dev, float* w32_dev, void* hip_stream);
 
-/* Serving: a request loop with continuous batching. Requests are admitted in
- * arrival order while their workspace fits in hbm_budget_bytes and one of
- * max_slots execution slots (each its own stream) is free; admitted requests
- * run concurrently on the device. A scheduler thread owns the GPU side.
- * Errors: INVALID (budget 0, max_slots outside 1..64), NOMEM, HIP. */
+/* Serving: a request loop with continuous batching for the repeated log-CDF
+ * evaluations of Section 4 (one Gaussian CDF per temporal replicate and per
+ * scale-mixture node, eqs. (9)-(11), as a likelihood optimizer or an MCMC chain
+ * issues them). The server reserves one device arena of hbm_budget_bytes and
+ * max_slots execution slots (each a stream with two side streams). Whenever a
+ * slot is free, a scheduler thread admits the queued requests in arrival order
+ * as one group - as many as fit in the arena, up to 64 requests - and runs
+ * them as one batch: one QMC launch per conditioning-set size over all of them.
+ * Groups on different slots overlap on the device. A request's result is the
+ * same alone and in any group. Errors: INVALID (budget 0, max_slots outside
+ * 1..64), NOMEM, HIP. */
 vecchia_status vecchia_server_create(size_t hbm_budget_bytes, int32_t max_slots, vecchia_server_t* out);
 
-/* Queue one log-CDF request; returns at once with a ticket. x_dev must stay
- * valid and unchanged until the request is done. Errors: INVALID (bad
- * arguments), NOMEM (the request alone exceeds the HBM budget). */
+/* Queue one log-CDF request (the vecchia_logcdf of Section 2.2, eq. (6), at
+ * thresholds x / scale, eq. (9)); returns at once with a ticket. The server
+ * reads x_dev on its own streams, which are not ordered after the caller's:
+ * x_dev must hold its final values when vecchia_submit is called (the stream
+ * that wrote it synchronized) and stay unchanged until the request is done.
+ * Errors: INVALID (bad arguments), NOMEM (the request alone exceeds the HBM
+ * budget). */
 vecchia_status vecchia_submit(vecchia_server_t server, vecchia_plan_t plan, const double* x_dev,
                               double scale, const vecchia_cov* cov_override, const vecchia_qmc* q,
                               uint64_t* ticket);
 
-/* Non-blocking. *done = 1 and {log F, SE} when finished (the ticket is then
- * released), else *done = 0. latency_s (may be NULL): submit-to-completion
- * seconds. Errors: INVALID (unknown ticket), NOT_PD (the request's covariance
- * failed; the ticket is released). */
+/* Result of a request (Section 2.2, eq. (6), with its Section 3.1 log-scale
+ * sum). Non-blocking. *done = 1 and {log F, SE} when finished (the ticket is
+ * then released), else *done = 0. latency_s (may be NULL): submit-to-completion
+ * seconds, for the serving loop's latency figures. Errors: INVALID (unknown
+ * ticket), NOT_PD (the request's covariance failed; the ticket is released). */
 vecchia_status vecchia_poll(vecchia_server_t server, uint64_t ticket, double* logF, double* se,
                             int32_t* done, double* latency_s);
 
-/* Stop the scheduler after in-flight work drains and free the server. */
+/* Stop the scheduler after queued and in-flight requests drain (the serving
+ * loop of Section 4's repeated evaluations) and free the server. */
 vecchia_status vecchia_server_destroy(vecchia_server_t server);
 
 #ifdef __cplusplus
