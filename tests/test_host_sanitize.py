@@ -1,8 +1,11 @@
-"""Host code built with AddressSanitizer and UndefinedBehaviorSanitizer by g++:
+"""Host code built with sanitizers by g++:
 the ordering code (the plan's step a0) on random, tied, duplicated and
 degenerate inputs, whose permutations must equal the oracle's (brute-force
 definitions), and the serving loop's first-fit arena against a brute-force
-model. The sanitizers must stay silent. Host code only."""
+model, under AddressSanitizer and UndefinedBehaviorSanitizer; the serving
+loop's scheduler (submit, poll, grouping, retirement, shutdown) with many
+client threads against a simulated device, under ThreadSanitizer and under
+AddressSanitizer. The sanitizers must stay silent. Host code only."""
 import os
 import shutil
 import subprocess
@@ -77,3 +80,23 @@ def test_serving_arena_against_a_brute_force_model(tmp_path):
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=1", UBSAN_OPTIONS="halt_on_error=1")
     r = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=300)
     assert r.returncode == 0 and r.stdout.strip() == "ok", (r.stdout[-500:], r.stderr[-2000:])
+
+
+@pytest.mark.parametrize("sanitizer", ["thread", "address,undefined"])
+def test_serving_scheduler_under_sanitizers(tmp_path, sanitizer):
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("g++ not available")
+    exe = str(tmp_path / "sched_check")
+    cmd = [gxx, "-std=c++17", "-O1", "-g", "-fno-omit-frame-pointer", f"-fsanitize={sanitizer}", "-I", CSRC,
+           os.path.join(ROOT, "tests", "host_sanitize", "sched_check.cpp"), "-o", exe, "-lpthread"]
+    if "undefined" in sanitizer:
+        cmd.insert(5, "-fno-sanitize-recover=undefined")
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        pytest.skip("sanitizer build unavailable: " + r.stderr[-300:])
+    env = dict(os.environ, TSAN_OPTIONS="halt_on_error=1:second_deadlock_stack=1",
+               ASAN_OPTIONS="detect_leaks=1:abort_on_error=1", UBSAN_OPTIONS="halt_on_error=1")
+    r = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=300)
+    assert r.returncode == 0 and r.stdout.strip() == "ok", (r.stdout[-1500:], r.stderr[-3000:])
+    assert "ThreadSanitizer" not in r.stderr and "AddressSanitizer" not in r.stderr, r.stderr[-3000:]
