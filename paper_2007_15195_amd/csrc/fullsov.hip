@@ -3,7 +3,7 @@
 // against (Section 3.1, Figures 1-4), on the plan's ordering and covariance.
 //
 //   1. full_cov_build: the dense D x D covariance (plan order, FP64) and b = x / scale;
-//   2. blocked right-looking Cholesky, block 32: chol_diag (one wave, LDS),
+//   2. blocked right-looking Cholesky, block 32: chol_diag (one wave, rows in registers),
 //      chol_panel (one thread per row below the block), chol_update (64 x 64
 //      tiles of the trailing lower triangle on the FP64 matrix cores);
 //   3. chol_mirror copies L into the upper triangle (L^T), so that a column of L
@@ -73,35 +73,33 @@ __global__ __launch_bounds__(256) void full_cov_build(CovArgs a, int64_t D, doub
   if (j == 0) b[i] = a.x[a.perm[i]] * a.inv_scale;
 }
 
-// Factor the diagonal block [k0, k0 + n) in place (one wave; left-looking, one
-// lane per row). A non-positive pivot writes NaN on the diagonal.
+// Factor the diagonal block [k0, k0 + n) in place (one wave; right-looking,
+// lane r holds row r of the block in registers). Column j's pivot is broadcast
+// from lane j, the column goes through LDS, and each lane updates its own row
+// with independent FMAs. A non-positive pivot writes NaN on the diagonal.
 __global__ __launch_bounds__(64) void chol_diag(double* __restrict__ A, int64_t D, int64_t k0, int n) {
-  __shared__ double C[kCholB][kCholB + 1];
-  __shared__ double piv;
+  __shared__ double col[kCholB];
   const int lane = threadIdx.x;
-  for (int idx = lane; idx < n * n; idx += 64) {
-    const int r = idx / n, c = idx - r * n;
-    if (c <= r) C[r][c] = A[(k0 + r) * D + k0 + c];
-  }
-  __syncthreads();
-  for (int j = 0; j < n; ++j) {
-    double s = 0.0;
-    if (lane >= j && lane < n) {
-      s = C[lane][j];
-      for (int p = 0; p < j; ++p) s -= C[lane][p] * C[j][p];
+  double c[kCholB];
+#pragma unroll
+  for (int p = 0; p < kCholB; ++p) c[p] = (lane < n && p <= lane) ? A[(k0 + lane) * D + k0 + p] : 0.0;
+#pragma unroll
+  for (int j = 0; j < kCholB; ++j) {
+    if (j < n) {
+      const double d = __shfl(c[j], j, 64);
+      const double ljj = d > 0.0 ? sqrt(d) : __builtin_nan("");
+      c[j] = lane > j ? c[j] / ljj : (lane == j ? ljj : c[j]);
+      if (lane < kCholB) col[lane] = c[j];
+      __syncthreads();
+#pragma unroll
+      for (int p = j + 1; p < kCholB; ++p)
+        if (p <= lane) c[p] -= c[j] * col[p];
+      __syncthreads();   // every lane has read the column before the next one is written
     }
-    if (lane == j) piv = s;
-    __syncthreads();
-    const double d = piv;
-    const double ljj = d > 0.0 ? sqrt(d) : __builtin_nan("");
-    if (lane > j && lane < n) C[lane][j] = s / ljj;
-    if (lane == j) C[j][j] = ljj;
-    __syncthreads();
   }
-  for (int idx = lane; idx < n * n; idx += 64) {
-    const int r = idx / n, c = idx - r * n;
-    if (c <= r) A[(k0 + r) * D + k0 + c] = C[r][c];
-  }
+#pragma unroll
+  for (int p = 0; p < kCholB; ++p)
+    if (lane < n && p <= lane) A[(k0 + lane) * D + k0 + p] = c[p];
 }
 
 // Rows i >= k0 + n: L[i, k0:k0+n] = A[i, k0:k0+n] L_kk^-T (forward substitution).
@@ -235,6 +233,7 @@ __global__ __launch_bounds__(64 * NW) void full_sov(const double* __restrict__ L
                                                     double2* __restrict__ part, SovSizes a) {
   __shared__ double T[NW][kFsB][kFsWavePts + 1];
   __shared__ double Lb[kFsB * (kFsB + 1) / 2];   // the block's lower triangle, packed by rows
+  __shared__ double dinv[kFsB];                  // reciprocals of the block's diagonal
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int r = blockIdx.y;
   const int64_t D = a.D, S = a.S, N = a.N;
@@ -297,13 +296,21 @@ __global__ __launch_bounds__(64 * NW) void full_sov(const double* __restrict__ L
       const int c = idx - q * (q + 1) / 2;
       Lb[idx] = q < nb ? L[(j0 + q) * D + j0 + c] : 0.0;
     }
+    for (int q = tid; q < kFsB; q += 64 * NW) dinv[q] = q < nb ? 1.0 / L[(j0 + q) * D + j0 + q] : 0.0;
     __syncthreads();
 #pragma unroll 1
     for (int q = 0; q < nb; ++q) {
       // every lane group evaluates the same point's factor; group 0 keeps it
-      const double t = Tw[q][m] / Lb[q * (q + 1) / 2 + q];
+      const double t = Tw[q][m] * dinv[q];
       const double e = ncdf_full(t);
-      lp += log_ncdf(t);
+      // log Phi(t) from Phi(t) itself while Phi(t) > 1e-197 (its relative
+      // error is then that of the log's absolute error); the scaled
+      // complementary form only where some lane's limit is at or below -30
+      double lt = log(e);
+      if (__builtin_expect(__any(t <= -30.0), 0)) {
+        if (t <= -30.0) lt = log_ncdf(t);
+      }
+      lp += lt;
       const int64_t dim = j0 + q;
       if (dim < D - 1) {
         const uint64_t Sh = splitmix64(a.seed, (1ULL << 63) | ((uint64_t)r << 32) | (uint64_t)dim);
@@ -341,40 +348,58 @@ int full_sov_waves(int64_t N, int64_t R, int n_cu) {
   return 1;
 }
 
-// log of the mean over points of shift r, from its workgroup partials (in order)
-__device__ double shift_logmean(const double2* __restrict__ part, int nblk, int r, int64_t N) {
-  double M = -HUGE_VAL;
-  for (int k = 0; k < nblk; ++k) M = fmax(M, part[(int64_t)r * nblk + k].x);
-  if (!(M > -HUGE_VAL)) return M;
-  double sum = 0.0;
-  for (int k = 0; k < nblk; ++k) {
-    const double2 v = part[(int64_t)r * nblk + k];
-    if (v.x > -HUGE_VAL) sum += v.y * exp(v.x - M);
-  }
-  return M + log(sum) - log((double)N);
-}
-
-// One thread: the shifts' log means, then log F and the delta-method SE.
-__global__ void full_final(const double2* __restrict__ part, int nblk, int R, int64_t N, double* __restrict__ out) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// One workgroup of 256: per shift r, l_r = log mean over points from the waves'
+// {max, sum exp} partials (strided partial reductions, then a fixed tree, so the
+// result does not depend on scheduling); then log F = log mean_r exp(l_r) and
+// the delta-method SE over shifts.
+__global__ __launch_bounds__(256) void full_final(const double2* __restrict__ part, int nblk, int R, int64_t N,
+                                                  double* __restrict__ out) {
+  __shared__ double red[256];
+  const int tid = threadIdx.x;
+  auto tree = [&](double v, bool is_max) {
+    red[tid] = v;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if (tid < o) red[tid] = is_max ? fmax(red[tid], red[tid + o]) : red[tid] + red[tid + o];
+      __syncthreads();
+    }
+    const double res = red[0];
+    __syncthreads();
+    return res;
+  };
+  auto logmean = [&](int r) {
+    const double2* __restrict__ pr = part + (int64_t)r * nblk;
+    double mx = -HUGE_VAL;
+    for (int k = tid; k < nblk; k += 256) mx = fmax(mx, pr[k].x);
+    const double M = tree(mx, true);
+    if (!(M > -HUGE_VAL)) return M;
+    double sm = 0.0;
+    for (int k = tid; k < nblk; k += 256) {
+      const double2 v = pr[k];
+      if (v.x > -HUGE_VAL) sm += v.y * exp(v.x - M);
+    }
+    return M + log(tree(sm, false)) - log((double)N);
+  };
   double top = -HUGE_VAL;
-  for (int r = 0; r < R; ++r) top = fmax(top, shift_logmean(part, nblk, r, N));
+  for (int r = 0; r < R; ++r) top = fmax(top, logmean(r));
   double logF = top, se = __builtin_nan("");
   if (top > -HUGE_VAL) {
     double sum = 0.0;
-    for (int r = 0; r < R; ++r) sum += exp(shift_logmean(part, nblk, r, N) - top);
+    for (int r = 0; r < R; ++r) sum += exp(logmean(r) - top);
     logF = top + log(sum) - log((double)R);
     if (R > 1) {
       double acc = 0.0;
       for (int r = 0; r < R; ++r) {
-        const double d = exp(shift_logmean(part, nblk, r, N) - logF) - 1.0;
+        const double d = exp(logmean(r) - logF) - 1.0;
         acc += d * d;
       }
       se = sqrt(acc / ((double)R * (R - 1)));
     }
   }
-  out[0] = logF;
-  out[1] = se;
+  if (tid == 0) {
+    out[0] = logF;
+    out[1] = se;
+  }
 }
 
 }  // namespace
@@ -471,7 +496,7 @@ extern "C" vecchia_status vecchia_full_logcdf(vecchia_plan_t plan, const double*
     e = hipGetLastError();
   }
   if (e == hipSuccess) {
-    hipLaunchKernelGGL(full_final, dim3(1), dim3(64), 0, s, part, (int)nblk * nw, (int)R, N, out_dev);
+    hipLaunchKernelGGL(full_final, dim3(1), dim3(256), 0, s, part, (int)nblk * nw, (int)R, N, out_dev);
     e = hipGetLastError();
   }
   if (e != hipSuccess) return hip_error(e, "full-dimension launch");

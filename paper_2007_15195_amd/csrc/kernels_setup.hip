@@ -1,6 +1,7 @@
 // term_setup: steps a2-a3 of every Vecchia term (Section 2.2, eq. (6)).
 //
-// One wave per term. The term's variables are its conditioning set N_i (in the
+// One wave per term, with LDS blocks sized for the batch's largest term (16, 32
+// or 64 variables). The term's variables are its conditioning set N_i (in the
 // plan's (d^2, index) order) followed by i itself. The wave gathers their
 // locations and thresholds b = x / scale, builds the covariance block C in LDS
 // (FP64), factors C = L L^T in place (left-looking, one lane per row) and writes
@@ -51,14 +52,17 @@ __device__ __forceinline__ int find_inst(const int64_t* __restrict__ bases, int 
 
 // Set-up of global term t by the calling wave (one wave per block). redo: the
 // term of an FP32 evaluation is run again in FP64; only its FP64 rows are
-// written, in place of its FP32 rows.
+// written, in place of its FP32 rows. KV: the most variables of any term of
+// the batch (16, 32 or 64); the LDS blocks are sized for it, so that smaller
+// conditioning sets fit more waves on a compute unit.
+template <int KV>
 __device__ __forceinline__ void setup_term(const InstDesc* __restrict__ insts, int n_inst,
                                            const int64_t* __restrict__ term_bases, Aux64* __restrict__ aux64,
                                            Aux32* __restrict__ aux32, int64_t t, bool redo) {
-  __shared__ double C[kMaxVars][kMaxVars + 1];
-  __shared__ double px[kMaxVars], py[kMaxVars], pb[kMaxVars], pw[kMaxVars];
+  __shared__ double C[KV][KV + 1];
+  __shared__ double px[KV], py[KV], pb[KV], pw[KV];
   __shared__ long long pslot;
-  __shared__ int pv[kMaxVars];
+  __shared__ int pv[KV];
   __shared__ double piv;
   const int lane = threadIdx.x;
   const int ii = find_inst(term_bases, n_inst, t);
@@ -68,6 +72,10 @@ __device__ __forceinline__ void setup_term(const InstDesc* __restrict__ insts, i
   const int boff = blk ? I.bvar_off[i] : 0;
   const int k = blk ? I.bvar_off[i + 1] - boff - 1 : I.kcnt[i];
   const int n = k + 1;
+  if (n > KV) {   // the host sizes KV for every term of the batch; never taken
+    if (lane == 0) atomicMin((long long*)I.bad_term, (long long)i);
+    return;
+  }
   // variable slot of each lane's neighbour: observed neighbours first (censored
   // plans only), each group in the stored order, i last
   const int64_t v = blk ? (lane < n ? (int64_t)I.bvars[boff + lane] : 0)
@@ -231,15 +239,17 @@ __device__ __forceinline__ void setup_term(const InstDesc* __restrict__ insts, i
   }
 }
 
+template <int KV>
 __global__ __launch_bounds__(64) void term_setup(const InstDesc* __restrict__ insts, int n_inst,
                                                  const int64_t* __restrict__ term_bases,
                                                  Aux64* __restrict__ aux64,
                                                  Aux32* __restrict__ aux32, int64_t term_base) {
-  setup_term(insts, n_inst, term_bases, aux64, aux32, term_base + (int64_t)blockIdx.x, false);
+  setup_term<KV>(insts, n_inst, term_bases, aux64, aux32, term_base + (int64_t)blockIdx.x, false);
 }
 
 // The re-run list's terms, one per wave in turn; every wave leaves once the
 // list (read once, written by the finalize before this launch) is used up.
+template <int KV>
 __global__ __launch_bounds__(64) void term_setup_redo(const InstDesc* __restrict__ insts, int n_inst,
                                                       const int64_t* __restrict__ term_bases,
                                                       Aux64* __restrict__ aux64, Aux32* __restrict__ aux32,
@@ -247,33 +257,59 @@ __global__ __launch_bounds__(64) void term_setup_redo(const InstDesc* __restrict
                                                       const int64_t* __restrict__ count, int64_t cap) {
   const int64_t n = min(*count, cap);
   for (int64_t e = blockIdx.x; e < n; e += gridDim.x) {
-    setup_term(insts, n_inst, term_bases, aux64, aux32, (int64_t)list[e], true);
+    setup_term<KV>(insts, n_inst, term_bases, aux64, aux32, (int64_t)list[e], true);
     __syncthreads();   // the next term reuses the LDS blocks
   }
 }
 
 }  // namespace
 
-hipError_t launch_setup(const InstDesc* d_insts, int n_inst, const int64_t* d_term_bases,
-                        int64_t total_terms, Aux64* aux64, Aux32* aux32, hipStream_t s) {
-  if (total_terms <= 0) return hipSuccess;
-  if (total_terms > 0x7fffffffLL) return hipErrorInvalidValue;
+// Tile size for the batch's largest term: 16, 32 or 64 variables.
+static int setup_tile(int max_vars) { return max_vars <= 16 ? 16 : max_vars <= 32 ? 32 : 64; }
+
+template <int KV>
+static hipError_t launch_setup_kv(const InstDesc* d_insts, int n_inst, const int64_t* d_term_bases,
+                                  int64_t total_terms, Aux64* aux64, Aux32* aux32, hipStream_t s) {
   constexpr int64_t kPer = kMaxLaunchThreads / 64;   // terms (one wave each) per launch
   for (int64_t b = 0; b < total_terms; b += kPer) {
     const unsigned n = (unsigned)(total_terms - b < kPer ? total_terms - b : kPer);
-    hipLaunchKernelGGL(term_setup, dim3(n), dim3(64), 0, s, d_insts, n_inst, d_term_bases, aux64, aux32, b);
+    hipLaunchKernelGGL(term_setup<KV>, dim3(n), dim3(64), 0, s, d_insts, n_inst, d_term_bases, aux64, aux32, b);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
 }
 
-hipError_t launch_setup_redo(const InstDesc* d_insts, int n_inst, const int64_t* d_term_bases, Aux64* aux64,
-                             Aux32* aux32, const int32_t* list, const int64_t* count, int64_t cap, hipStream_t s) {
+hipError_t launch_setup(const InstDesc* d_insts, int n_inst, const int64_t* d_term_bases,
+                        int64_t total_terms, int max_vars, Aux64* aux64, Aux32* aux32, hipStream_t s) {
+  if (total_terms <= 0) return hipSuccess;
+  if (total_terms > 0x7fffffffLL || max_vars < 1 || max_vars > kMaxVars) return hipErrorInvalidValue;
+  switch (setup_tile(max_vars)) {
+    case 16: return launch_setup_kv<16>(d_insts, n_inst, d_term_bases, total_terms, aux64, aux32, s);
+    case 32: return launch_setup_kv<32>(d_insts, n_inst, d_term_bases, total_terms, aux64, aux32, s);
+    default: return launch_setup_kv<64>(d_insts, n_inst, d_term_bases, total_terms, aux64, aux32, s);
+  }
+}
+
+hipError_t launch_setup_redo(const InstDesc* d_insts, int n_inst, const int64_t* d_term_bases, int max_vars,
+                             Aux64* aux64, Aux32* aux32, const int32_t* list, const int64_t* count, int64_t cap,
+                             hipStream_t s) {
   if (cap <= 0) return hipSuccess;
+  if (max_vars < 1 || max_vars > kMaxVars) return hipErrorInvalidValue;
   const unsigned grid = (unsigned)(cap < 1024 ? cap : 1024);
-  hipLaunchKernelGGL(term_setup_redo, dim3(grid), dim3(64), 0, s, d_insts, n_inst, d_term_bases, aux64, aux32,
-                     list, count, cap);
+  switch (setup_tile(max_vars)) {
+    case 16:
+      hipLaunchKernelGGL(term_setup_redo<16>, dim3(grid), dim3(64), 0, s, d_insts, n_inst, d_term_bases, aux64,
+                         aux32, list, count, cap);
+      break;
+    case 32:
+      hipLaunchKernelGGL(term_setup_redo<32>, dim3(grid), dim3(64), 0, s, d_insts, n_inst, d_term_bases, aux64,
+                         aux32, list, count, cap);
+      break;
+    default:
+      hipLaunchKernelGGL(term_setup_redo<64>, dim3(grid), dim3(64), 0, s, d_insts, n_inst, d_term_bases, aux64,
+                         aux32, list, count, cap);
+  }
   return hipGetLastError();
 }
 

@@ -267,6 +267,7 @@ vecchia_status Batch::create(const std::vector<vecchia_plan_s*>& plans,
     const int passes = qmcs[j].flags == VECCHIA_QMC_INDEPENDENT ? 2 : 1;   // a second lattice for the denominators
     const int prec = qmcs[j].precision;
     const int nv = P->block > 0 ? P->block_nv : P->m + 1;   // variables per term, at most
+    b->max_vars_ = std::max(b->max_vars_, nv);
     // FP32 rows leave room for the FP64 rows of a term handed to the FP64 kernels
     const int stride = prec == VECCHIA_FP32_LOOP ? 2 * (int)align_up((size_t)nv * (nv + 1) / 2, 2)
                                                  : (int)align_up((size_t)nv * (nv + 1) / 2, 2);
@@ -470,7 +471,7 @@ vecchia_status Batch::enqueue(hipStream_t s, bool allow_profile) {
   hipError_t e = launch_fill_i64(d_bad_, n, INT64_MAX, s);
   if (e == hipSuccess && any_f32_) e = launch_fill_i64(d_pctr_, 4, 0, s);
   if (e == hipSuccess)
-    e = launch_setup(d_desc_, n, d_term_bases_, total_terms_, d_aux64_, d_aux32_, s);
+    e = launch_setup(d_desc_, n, d_term_bases_, total_terms_, max_vars_, d_aux64_, d_aux32_, s);
   // fork: side streams start after the setup kernel
   const int n_side = side_[0] ? std::min<int>((int)launches_.size() - 1, kSideStreams) : 0;
   if (e == hipSuccess && n_side > 0) {
@@ -510,7 +511,7 @@ vecchia_status Batch::enqueue(hipStream_t s, bool allow_profile) {
   // rows, FP64 items and their finalize (three grids that exit at once when
   // the list is empty)
   if (e == hipSuccess && redo)
-    e = launch_setup_redo(d_desc_, n, d_term_bases_, d_aux64_, d_aux32_, d_plist_ + plist_cap_, d_pctr_ + 2,
+    e = launch_setup_redo(d_desc_, n, d_term_bases_, max_vars_, d_aux64_, d_aux32_, d_plist_ + plist_cap_, d_pctr_ + 2,
                           plist_cap_, s);
   if (e == hipSuccess && redo)
     e = launch_qmc_promoted(d_desc_, n, d_term_bases_, d_aux64_, d_Z_, d_sums_, d_plist_ + plist_cap_, d_pctr_ + 2,

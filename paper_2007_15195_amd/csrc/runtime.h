@@ -133,6 +133,7 @@ class Batch {
   int64_t* d_pctr_ = nullptr;
   int32_t plist_cap_ = 0;
   int32_t ipt_max_ = 0;
+  int max_vars_ = 1;   // most variables of any term (sizes the set-up kernel's tiles)
 
   static constexpr int kRing = 4;       // pinned descriptor staging slots
   InstDesc* h_stage_ = nullptr;

@@ -124,13 +124,16 @@ hipError_t launch_fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t s);
 // Copies `bytes` bytes of host memory to dst (device, 8-byte aligned) by kernels
 // that take them as arguments (no staging buffer, no memcpy node).
 hipError_t launch_store_bytes(void* dst, const void* src_host, size_t bytes, hipStream_t s);
+// max_vars: the most variables (conditioning set and the term's own) of any
+// term of the batch, at most kMaxVars; it sizes the kernel's LDS tiles.
 hipError_t launch_setup(const InstDesc* d_insts, int n_inst, const int64_t* d_term_bases,
-                        int64_t total_terms, Aux64* aux64, Aux32* aux32, hipStream_t s);
+                        int64_t total_terms, int max_vars, Aux64* aux64, Aux32* aux32, hipStream_t s);
 // The FP64 rows of the terms on a device-side list (count at *count, at most
 // cap entries): the re-runs of an FP32 evaluation. A persistent grid that
 // finds nothing to do when the list is empty.
-hipError_t launch_setup_redo(const InstDesc* d_insts, int n_inst, const int64_t* d_term_bases, Aux64* aux64,
-                             Aux32* aux32, const int32_t* list, const int64_t* count, int64_t cap, hipStream_t s);
+hipError_t launch_setup_redo(const InstDesc* d_insts, int n_inst, const int64_t* d_term_bases, int max_vars,
+                             Aux64* aux64, Aux32* aux32, const int32_t* list, const int64_t* count, int64_t cap,
+                             hipStream_t s);
 // block: the launch's instances are block plans (denominator split per term).
 hipError_t launch_qmc(int K, int precision, bool block, const InstDesc* d_insts, const RangeDesc* d_ranges,
                       int n_ranges, int64_t n_items, const Aux64* aux64, const Aux32* aux32,
