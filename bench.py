@@ -318,8 +318,17 @@ def bench_comparator(V, torch, args):
             q64 = V.make_qmc(N, R, 11, V.VECCHIA_FP64)
             sec = _timed(torch, lambda: V.vecchia_full_logcdf(plan, x, q64, out, stream=sp), 1)
             o = out.cpu().numpy()
+            # the product-and-recursion kernel alone (HIP events on its stream)
+            V.vecchia_profile_reset()
+            V.vecchia_profile_enable(1)
+            V.vecchia_full_logcdf(plan, x, q64, out, stream=sp)
+            torch.cuda.synchronize()
+            V.vecchia_profile_enable(0)
+            k_ms, _, k_fma = V.vecchia_profile_read(V.VECCHIA_PROFILE_FULL_SOV, V.VECCHIA_FP64)
+            V.vecchia_profile_reset()
             row["full_sov_fp64"] = {"seconds": sec, "logF": float(o[0]), "se": float(o[1]),
-                                    "points_per_s": N * R / sec}
+                                    "points_per_s": N * R / sec, "kernel_ms": k_ms,
+                                    "kernel_tflops": 2.0 * k_fma / (k_ms * 1e-3) / 1e12 if k_ms > 0 else None}
             V.vecchia_plan_destroy(plan)
             for m in (5, 10, 30, 50):
                 p = V.vecchia_plan(locs, V.VECCHIA_ORDER_MAXMIN, m, cov, stream=sp)
@@ -344,8 +353,11 @@ def bench_comparator(V, torch, args):
     big = [r for r in rows if r["D"] == 10_000]
     summary = {}
     if big:
+        tf = [r["full_sov_fp64"]["kernel_tflops"] for r in big if r["full_sov_fp64"]["kernel_tflops"]]
         summary = {"full_sov_seconds_100x100": [r["full_sov_fp64"]["seconds"] for r in big],
-                   "vecchia_m30_fp32_seconds_100x100": [r["vecchia_m30_fp32"]["seconds"] for r in big]}
+                   "vecchia_m30_fp32_seconds_100x100": [r["vecchia_m30_fp32"]["seconds"] for r in big],
+                   "full_sov_kernel_ms_100x100": [round(r["full_sov_fp64"]["kernel_ms"], 2) for r in big],
+                   "full_sov_kernel_fp64_frac_100x100": [round(t / FP64_PEAK_TFLOPS, 4) for t in tf]}
     return {"workload": "exp_grids_unit_spacing_comparator", "n_points": N, "n_shifts": R,
             "columns": "full: [s, logF, se]; mK: [fp32 s, fp64 s, fp32 logF]", "rows": table, **summary}
 

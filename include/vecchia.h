@@ -310,7 +310,12 @@ vecchia_status vecchia_batch_destroy(vecchia_batch_t batch);
  * A QMC launch covers the terms of one conditioning-set size K in one
  * precision. vecchia_profile_read waits for the recorded launches of (K,
  * precision) and returns their summed milliseconds, launch count and SOV steps
- * (sum over their terms of n_shifts * n_points * K). reset drops the records. */
+ * (sum over their terms of n_shifts * n_points * K). With K =
+ * VECCHIA_PROFILE_FULL_SOV and VECCHIA_FP64 it reads vecchia_full_logcdf's
+ * product-and-recursion kernel instead, whose "steps" are its FMAs over earlier
+ * dimensions, D (D - 1) / 2 per lattice point (Section 3.1's comparator).
+ * reset drops the records. */
+#define VECCHIA_PROFILE_FULL_SOV (-1)
 vecchia_status vecchia_profile_enable(int32_t on);
 vecchia_status vecchia_profile_read(int32_t K, int32_t precision, double* total_ms, int64_t* launches,
                                     int64_t* sov_steps);

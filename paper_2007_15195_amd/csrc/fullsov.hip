@@ -486,6 +486,11 @@ extern "C" vecchia_status vecchia_full_logcdf(vecchia_plan_t plan, const double*
   const int nw = full_sov_waves(N, R, n_cu);
   const int64_t P = (int64_t)kFsWavePts * nw;
   const unsigned nblk = (unsigned)((N + P - 1) / P);
+  // measurement hook: HIP events around the product-and-recursion kernel,
+  // recorded with its D(D-1)/2 FMAs per point
+  hipEvent_t pa = nullptr, pb = nullptr;
+  const bool prof = e == hipSuccess && profiling_enabled() && profile_events(&pa, &pb) == hipSuccess;
+  if (prof) e = hipEventRecord(pa, s);
   if (e == hipSuccess) {
     SovSizes sz{D, N, S, q->seed};
     const dim3 grid(nblk, (unsigned)R), block(64 * nw);
@@ -494,6 +499,10 @@ extern "C" vecchia_status vecchia_full_logcdf(vecchia_plan_t plan, const double*
     else if (nw == 2) hipLaunchKernelGGL(full_sov<2>, grid, block, 0, s, A, b, Zt, Y, part, sz);
     else hipLaunchKernelGGL(full_sov<1>, grid, block, 0, s, A, b, Zt, Y, part, sz);
     e = hipGetLastError();
+  }
+  if (prof && e == hipSuccess) {
+    e = hipEventRecord(pb, s);
+    if (e == hipSuccess) profile_record(VECCHIA_PROFILE_FULL_SOV, VECCHIA_FP64, pa, pb, D * (D - 1) / 2 * N * R);
   }
   if (e == hipSuccess) {
     hipLaunchKernelGGL(full_final, dim3(1), dim3(256), 0, s, part, (int)nblk * nw, (int)R, N, out_dev);

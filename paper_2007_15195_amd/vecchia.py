@@ -28,6 +28,7 @@ VECCHIA_MAX_SHIFTS = 65536
 VECCHIA_MAX_POINTS = 1 << 30
 VECCHIA_QMC_INDEPENDENT = 1
 VECCHIA_NOALLOC_SCRATCH_BYTES = 64 << 20
+VECCHIA_PROFILE_FULL_SOV = -1   # vecchia_profile_read key of the full-dimension kernel
 
 EXPORTED = [
     "vecchia_last_error", "vecchia_order", "vecchia_plan", "vecchia_plan_from_cov",

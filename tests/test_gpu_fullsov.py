@@ -127,3 +127,26 @@ def test_full_with_infinite_thresholds():
     got = _full(V, torch, plan, x, q)
     assert got[0] == -math.inf
     V.vecchia_plan_destroy(plan)
+
+
+def test_full_profile_hook_records_the_kernel():
+    # the measurement hook: one record per call, with D(D-1)/2 FMAs per point
+    torch = torch_cuda()
+    from paper_2007_15195_amd import vecchia as V
+    inst = W.small_random_instance(70, 5, 3, ordering=W.ORDER_MAXMIN, n_points=200, n_shifts=3)
+    plan = V.vecchia_plan(inst.locs, inst.ordering, inst.m, inst.cov)
+    x = torch.tensor(inst.x, dtype=torch.float64, device="cuda")
+    out = torch.empty(2, dtype=torch.float64, device="cuda")
+    q = V.make_qmc(200, 3, 5, V.VECCHIA_FP64)
+    V.vecchia_profile_reset()
+    V.vecchia_profile_enable(1)
+    try:
+        V.vecchia_full_logcdf(plan, x, q, out)
+        torch.cuda.synchronize()
+    finally:
+        V.vecchia_profile_enable(0)
+    ms, launches, fmas = V.vecchia_profile_read(V.VECCHIA_PROFILE_FULL_SOV, V.VECCHIA_FP64)
+    V.vecchia_profile_reset()
+    V.vecchia_plan_destroy(plan)
+    assert launches == 1 and ms > 0.0
+    assert fmas == 70 * 69 // 2 * 200 * 3
