@@ -13,12 +13,14 @@
 //      64. The part of each block's limits that comes from earlier dimensions,
 //      b_a - sum_{c<j0} L_ac y_c, is a product of 64 rows of L by the earlier y
 //      of the workgroup's points, run on the FP64 matrix cores
-//      (v_mfma_f64_16x16x4); the block's own recursion then runs from LDS, one
-//      lane per point:
+//      (v_mfma_f64_16x16x4); the block's own recursion then runs from LDS in
+//      each wave (its four 16-lane groups evaluate the same 16 points, and each
+//      group updates every fourth later row):
 //          e_a = Phi(t_a), log prod += log Phi(t_a), y_a = Phi^-1(max(w_a e_a, DBL_MIN)).
-//      Each workgroup leaves {max, sum exp(. - max)} of its points' log products;
-//   5. full_final: per shift l_r = log mean over points, then
-//      log F = log mean_r exp(l_r) and the delta-method SE over the shifts.
+//      Each wave leaves {max, sum exp(. - max)} of its points' log products;
+//   5. full_final (one workgroup, fixed-order trees): per shift l_r = log mean
+//      over points, then log F = log mean_r exp(l_r) and the delta-method SE
+//      over the shifts.
 // Lattice: Z_j from the first D - 1 primes; the shift of dimension j in
 // replicate r is SplitMix64 output 2^63 + r 2^32 + j of the call's seed.
 #include <hip/hip_runtime.h>
