@@ -256,8 +256,9 @@ __global__ __launch_bounds__(64 * NW) void full_sov(const double* __restrict__ L
     // rows past D in a last, ragged block read other entries of L (in the array
     // while j0 > 0, since then D > kFsB); their sums are never used
     const double* __restrict__ aA = L + j0 + m + (int64_t)kq * D;
-    // j0 is a multiple of kFsB: whole steps of 4 earlier dimensions; the loads of
-    // step c0 + 4 are issued before the MFMAs of step c0 (two register sets)
+    // j0 is a multiple of kFsB: whole steps of 4 earlier dimensions (a multiple
+    // of 16 steps); the loads of step c0 + 4 are issued before the MFMAs of
+    // step c0 (two register sets)
     const int steps = (int)(j0 / 4);
     double av[2][4], bv[2];
     auto load_step = [&](int st, int buf) {
@@ -271,15 +272,19 @@ __global__ __launch_bounds__(64 * NW) void full_sov(const double* __restrict__ L
 #pragma unroll
       for (int i = 0; i < 4; ++i) acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[buf][i], bv[buf], acc[i], 0, 0, 0);
     };
-    if (steps > 0) load_step(0, 0);
-    int st = 0;
-    for (; st + 2 <= steps; st += 2) {
-      load_step(st + 1, 1);
-      mfma_step(0);
-      if (st + 2 < steps) load_step(st + 2, 0);
-      mfma_step(1);
+    // the loads past the last step re-read it: with every load unconditional
+    // the compiler's wait counts stay exact across the loop
+    if (steps > 0) {
+      load_step(0, 0);
+      for (int st = 0; st < steps; st += 2) {
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          const int nx = st + u + 1;
+          load_step(nx < steps ? nx : steps - 1, (u + 1) & 1);
+          mfma_step(u);
+        }
+      }
     }
-    if (st < steps) mfma_step(0);
     // acc[i] element e (the MFMA's output layout): row 16 i + 4 e + kq of the
     // block, point m of the wave's tile
 #pragma unroll
