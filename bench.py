@@ -75,7 +75,8 @@ TRANS_PER_STEP = {"exp": 1, "log": 1, "rcp": 2, "sqrt": 1}
 # kernel sources it was taken on (a changed kernel makes its figures stale).
 PMC_F32 = os.path.join(ROOT, "profiles", "qmc_f32_k10_uniform2500_pmc.md")
 PMC_F64 = os.path.join(ROOT, "profiles", "qmc_f64_k10_uniform2500_pmc.md")
-KERNEL_SOURCES = ["kernels_qmc.hip", "device_math_f32.h", "lattice.h", "fp32_math_coeffs.h", "vecchia_internal.h"]
+KERNEL_SOURCES = ["kernels_qmc.hip", "device_math_f32.h", "lattice.h", "fp32_math_coeffs.h", "vecchia_internal.h",
+                  "device_math_f64.h", "fp64_math_coeffs.h"]
 
 
 def kernel_source_sha():

@@ -1,0 +1,47 @@
+// FP64 normal quantile for the FP64 SOV loops (the plain parity path, the
+// terms an FP32 evaluation hands over, and the full-dimension comparator).
+//
+// z = Phi^{-1}(q), q in (0, 1), in three pieces on p = min(q, 1 - q) (1 - q is
+// exact for q >= 1/2 in binary floating point):
+//   |q - 1/2| <= 0.425:  z = r P(x) / Q(x), r = q - 1/2, x = 0.425^2 - r^2;
+//   otherwise s = sqrt(-log p) and |z| = P(s - s0) / Q(s - s0), with s0 =
+//   sqrt(-log 0.075) for s <= 5 and s0 = 5 beyond, z taking the sign of r.
+// The rationals (fp64_math_coeffs.h, fitted by fit_fp64_math.py) have
+// coefficients of one sign, so Horner's rule evaluates them without
+// cancellation; the fits' relative error is below 2.1e-16 and the evaluated
+// function stays within a few units in the last place of the exact quantile
+// over p from 1/2 down to the smallest subnormal.
+#pragma once
+
+#include "fp64_math_coeffs.h"
+
+namespace vecchia {
+
+template <int N>
+__host__ __device__ __forceinline__ double horner64(const double (&c)[N], double x) {
+  double v = c[N - 1];
+#pragma unroll
+  for (int i = N - 2; i >= 0; --i) v = __builtin_fma(v, x, c[i]);
+  return v;
+}
+
+__host__ __device__ inline double ninv64(double q) {
+  const double r = q - 0.5;
+  if (__builtin_fabs(r) <= 0.425) {
+    const double x = __builtin_fma(-r, r, 0.180625);
+    return r * horner64(kNinvCentralP, x) / horner64(kNinvCentralQ, x);
+  }
+  const double p = r < 0.0 ? q : 1.0 - q;
+  const double s = sqrt(-log(p));
+  double z;
+  if (s <= 5.0) {
+    const double x = s - kNinvS1;
+    z = horner64(kNinvTail1P, x) / horner64(kNinvTail1Q, x);
+  } else {
+    const double x = s - 5.0;
+    z = horner64(kNinvTail2P, x) / horner64(kNinvTail2Q, x);
+  }
+  return r < 0.0 ? -z : z;
+}
+
+}  // namespace vecchia

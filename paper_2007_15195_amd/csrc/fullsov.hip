@@ -30,6 +30,7 @@
 #include <string>
 
 #include "device_cov.h"
+#include "device_math_f64.h"
 #include "lattice.h"
 #include "runtime.h"
 #include "vecchia.h"
@@ -199,10 +200,10 @@ __device__ __forceinline__ double log_ncdf(double t) {
                  : log1p(-0.5 * erfc(t * 0.70710678118654752440));
 }
 
-// The FP64 quantile stays out of line: inlined, it takes the recursion to the
-// full register file with spills.
+// The FP64 quantile (device_math_f64.h) stays out of line: inlined into the
+// recursion it would take registers the product loop needs.
 __device__ __forceinline__ double ncdf_full(double t) { return normcdf(t); }
-__device__ __noinline__ double ncdfinv_full(double u) { return normcdfinv(u); }
+__device__ __noinline__ double ncdfinv_full(double u) { return ninv64(u); }
 
 // L: D x D with L in the lower triangle and L^T in the upper; b: D limits;
 // Z: D - 1 generators; Y: (D - 1) x S (S = N R), the y of every point,

@@ -18,11 +18,12 @@
 // summed over lanes by a fixed butterfly, so an item's result does not depend on
 // where or with what else it runs.
 //
-// FP64 chain: the plain parity path (HIP's normcdf / normcdfinv).
+// FP64 chain: the plain parity path (HIP's normcdf, the quantile of device_math_f64.h).
 // FP32 chain: single precision with every factor e carried as a base-2 log
 // split em * 2^en; the products keep a separate exponent, so they cannot
 // underflow, and are rebuilt exactly in FP64 for the accumulation.
 #include "device_math_f32.h"
+#include "device_math_f64.h"
 #include "lattice.h"
 #include "vecchia_internal.h"
 
@@ -92,10 +93,10 @@ __device__ __forceinline__ double* item_out(const InstDesc& I, const Item& it, d
   return sums + 3 * (I.sums_base + (it.i * I.passes * I.n_shifts + it.r) * (int64_t)I.n_chunks + it.c);
 }
 
-// Out-of-line double-precision normal CDF and quantile (HIP device library),
-// so the unrolled chain does not inline several copies of them.
+// Out-of-line double-precision normal CDF (HIP device library) and quantile
+// (device_math_f64.h), so the unrolled chain does not inline several copies.
 __device__ __noinline__ double ncdf64(double t) { return normcdf(t); }
-__device__ __noinline__ double ncdfinv64(double u) { return normcdfinv(u); }
+__device__ __noinline__ double ncdfinv64(double u) { return ninv64(u); }
 
 template <int K, bool BLOCK>
 __device__ __forceinline__ void item_f64(const Item& it, const Aux64* __restrict__ aux64,

@@ -7,6 +7,7 @@
 #include <cmath>
 
 #include "device_math_f32.h"
+#include "device_math_f64.h"
 #include "lattice.h"
 #include "runtime.h"
 #include "vecchia.h"
@@ -45,7 +46,7 @@ __global__ __launch_bounds__(kProbeThreads) void probe_math(int what, int64_t n,
   } else if (what == VECCHIA_PROBE_PHI_F64) {
     o0 = normcdf(x);
   } else {
-    o0 = normcdfinv(x);
+    o0 = ninv64(x);
   }
   out[3 * i] = o0;
   out[3 * i + 1] = o1;

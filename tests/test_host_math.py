@@ -1,0 +1,79 @@
+"""The FP64 normal quantile of the FP64 loops (csrc/device_math_f64.h), built
+for the host by g++, against the exact quantile computed here with 40-digit
+arithmetic (mpmath): relative error within 1e-15 over q from the smallest
+subnormal to 1 - 2^-53, both sides of 1/2, the pieces' edges included. The
+same function runs on the GPU (test_gpu_device_math.py checks it there
+against SciPy). Host code only."""
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+
+mpmath = pytest.importorskip("mpmath")
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_2007_15195_amd", "csrc")
+
+
+def _exact_quantile(q):
+    """Phi^{-1}(q) to about 35 digits: erfinv for moderate q, else Newton on
+    log Phi(z) = log q (so tiny q keep their digits)."""
+    mpmath.mp.dps = 40
+    q = mpmath.mpf(q)
+    if q > mpmath.mpf("0.5"):
+        return -_exact_quantile(1 - q)
+    if q > mpmath.mpf("1e-8"):
+        return -mpmath.sqrt(2) * mpmath.erfinv(1 - 2 * q)
+    z = -mpmath.sqrt(-2 * mpmath.log(q))
+    for _ in range(200):
+        dz = (mpmath.log(mpmath.ncdf(z)) - mpmath.log(q)) / (mpmath.npdf(z) / mpmath.ncdf(z))
+        z -= dz
+        if abs(dz) < mpmath.mpf(10) ** -36:
+            break
+    return z
+
+
+def test_fp64_quantile_against_the_exact_quantile(tmp_path):
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("g++ not available")
+    exe = str(tmp_path / "ninv64_check")
+    r = subprocess.run([gxx, "-std=c++17", "-O2", "-mfma", "-I", CSRC,
+                        os.path.join(ROOT, "tests", "host_sanitize", "ninv64_check.cpp"), "-o", exe],
+                       capture_output=True, text=True)
+    if r.returncode != 0:
+        pytest.skip("host build unavailable: " + r.stderr[-300:])
+    rng = np.random.default_rng(7)
+    qs = np.concatenate([
+        rng.uniform(0.0, 1.0, 1500),
+        10.0 ** rng.uniform(-307.0, -0.3, 1500),
+        1.0 - 10.0 ** rng.uniform(-15.9, -0.3, 800),
+        [5e-324, 1e-320, 2.2250738585072014e-308, 1.4e-11, 0.0749999, 0.075, 0.0750001,
+         0.5 - 2.0 ** -53, 0.5 + 2.0 ** -53, 0.925, 1.0 - 2.0 ** -53],
+    ])
+    qs = qs[(qs > 0.0) & (qs < 1.0)]
+    text = "\n".join(repr(float(q)) for q in qs) + "\n"
+    out = subprocess.run([exe], input=text, capture_output=True, text=True, timeout=120)
+    assert out.returncode == 0, out.stderr
+    got = [float(v) for v in out.stdout.split()]
+    assert len(got) == len(qs)
+    worst = 0.0
+    for q, z in zip(qs, got):
+        ref = _exact_quantile(float(q))
+        if ref == 0:
+            assert abs(z) < 1e-300
+            continue
+        rel = float(abs((mpmath.mpf(z) - ref) / ref))
+        worst = max(worst, rel)
+        assert rel <= 1e-15, (float(q), z, float(ref), rel)
+    # the symmetry z(1 - q) = -z(q) holds exactly where 1 - q is exact
+    half = qs[qs < 0.5][:200]
+    text = "\n".join(repr(float(q)) for q in np.concatenate([half, 1.0 - half])) + "\n"
+    out = subprocess.run([exe], input=text, capture_output=True, text=True, timeout=120)
+    vals = np.array([float(v) for v in out.stdout.split()])
+    lo, hi = vals[:len(half)], vals[len(half):]
+    exact = (1.0 - (1.0 - half)) == half
+    assert np.array_equal(lo[exact], -hi[exact])
+    print("FP64 quantile on the host: max relative error %.2e over %d points" % (worst, len(qs)))
