@@ -200,9 +200,9 @@ __device__ __forceinline__ double log_ncdf(double t) {
                  : log1p(-0.5 * erfc(t * 0.70710678118654752440));
 }
 
-// The FP64 quantile (device_math_f64.h) stays out of line: inlined into the
-// recursion it would take registers the product loop needs.
-__device__ __forceinline__ double ncdf_full(double t) { return normcdf(t); }
+// The FP64 normal CDF and quantile of device_math_f64.h, both out of line:
+// inlined into the recursion they would take registers the product loop needs.
+__device__ __noinline__ double ncdf_full(double t) { return phi64(t); }
 __device__ __noinline__ double ncdfinv_full(double u) { return ninv64(u); }
 
 // L: D x D with L in the lower triangle and L^T in the upper; b: D limits;

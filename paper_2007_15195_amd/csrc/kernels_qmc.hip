@@ -18,7 +18,7 @@
 // summed over lanes by a fixed butterfly, so an item's result does not depend on
 // where or with what else it runs.
 //
-// FP64 chain: the plain parity path (HIP's normcdf, the quantile of device_math_f64.h).
+// FP64 chain: the plain parity path (the normal CDF and quantile of device_math_f64.h).
 // FP32 chain: single precision with every factor e carried as a base-2 log
 // split em * 2^en; the products keep a separate exponent, so they cannot
 // underflow, and are rebuilt exactly in FP64 for the accumulation.
@@ -93,9 +93,9 @@ __device__ __forceinline__ double* item_out(const InstDesc& I, const Item& it, d
   return sums + 3 * (I.sums_base + (it.i * I.passes * I.n_shifts + it.r) * (int64_t)I.n_chunks + it.c);
 }
 
-// Out-of-line double-precision normal CDF (HIP device library) and quantile
-// (device_math_f64.h), so the unrolled chain does not inline several copies.
-__device__ __noinline__ double ncdf64(double t) { return normcdf(t); }
+// Out-of-line double-precision normal CDF and quantile (device_math_f64.h), so
+// the unrolled chain does not inline several copies of them.
+__device__ __noinline__ double ncdf64(double t) { return phi64(t); }
 __device__ __noinline__ double ncdfinv64(double u) { return ninv64(u); }
 
 template <int K, bool BLOCK>

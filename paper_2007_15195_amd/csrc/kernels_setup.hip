@@ -35,6 +35,7 @@
 // with SE 0, and its rows get finite limits so the QMC kernels run a harmless
 // chain whose sums are never read.
 #include "device_cov.h"
+#include "device_math_f64.h"
 #include "fp32_math_coeffs.h"
 #include "vecchia_internal.h"
 
@@ -209,7 +210,7 @@ __device__ __forceinline__ void setup_term(const InstDesc* __restrict__ insts, i
       if (f32) aux32[t] = Aux32{0.0f, 0.0f, 0.0f, 0.0f};
     } else {
       const double b0 = pb[q] / C[q][q];
-      const double e0 = bad ? nan : normcdf(b0);
+      const double e0 = bad ? nan : phi64(b0);
       aux64[t].e0 = e0;
       aux64[t].lt0 = bad ? nan : log(e0);
       if (f32) {
@@ -226,7 +227,7 @@ __device__ __forceinline__ void setup_term(const InstDesc* __restrict__ insts, i
           a.em0 = (float)e0;
           a.en0 = 0.0f;
         }
-        a.ec0 = bad ? __builtin_nanf("") : (float)normcdf(-b0);
+        a.ec0 = bad ? __builtin_nanf("") : (float)phi64(-b0);
         aux32[t] = a;
       }
     }

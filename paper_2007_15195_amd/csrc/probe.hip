@@ -44,7 +44,7 @@ __global__ __launch_bounds__(kProbeThreads) void probe_math(int what, int64_t n,
     // the split path's quantile from log2 q = x directly (its exponents reach -2^20)
     o0 = ninv_tail_from_log2_split((float)x);
   } else if (what == VECCHIA_PROBE_PHI_F64) {
-    o0 = normcdf(x);
+    o0 = phi64(x);
   } else {
     o0 = ninv64(x);
   }

@@ -1,4 +1,4 @@
-"""The FP64 normal quantile of the FP64 loops (csrc/device_math_f64.h), built
+"""The FP64 normal quantile and CDF of the FP64 loops (csrc/device_math_f64.h), built
 for the host by g++, against the exact quantile computed here with 40-digit
 arithmetic (mpmath): relative error within 1e-15 over q from the smallest
 subnormal to 1 - 2^-53, both sides of 1/2, the pieces' edges included. The
@@ -77,3 +77,42 @@ def test_fp64_quantile_against_the_exact_quantile(tmp_path):
     exact = (1.0 - (1.0 - half)) == half
     assert np.array_equal(lo[exact], -hi[exact])
     print("FP64 quantile on the host: max relative error %.2e over %d points" % (worst, len(qs)))
+
+
+def test_fp64_normal_cdf_against_the_exact_cdf(tmp_path):
+    # phi64 (device_math_f64.h) on the host against mpmath's 40-digit normal
+    # CDF: relative error within 2e-15 wherever Phi(t) is a normal double,
+    # exact 0 / 1 at -inf / +inf, 0 below the smallest subnormal
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("g++ not available")
+    exe = str(tmp_path / "phi64_check")
+    r = subprocess.run([gxx, "-std=c++17", "-O2", "-mfma", "-I", CSRC,
+                        os.path.join(ROOT, "tests", "host_sanitize", "phi64_check.cpp"), "-o", exe],
+                       capture_output=True, text=True)
+    if r.returncode != 0:
+        pytest.skip("host build unavailable: " + r.stderr[-300:])
+    mpmath.mp.dps = 40
+    rng = np.random.default_rng(11)
+    ts = np.concatenate([rng.uniform(-37.5, 9.0, 2500), rng.uniform(-3.0, 3.0, 1000),
+                         [0.0, -0.0, 1e-300, -1e-300, -37.5, -38.4, 8.3, 38.5, -39.0, -1e6, np.inf, -np.inf]])
+    text = "\n".join(repr(float(t)) for t in ts) + "\n"
+    out = subprocess.run([exe], input=text, capture_output=True, text=True, timeout=120)
+    assert out.returncode == 0, out.stderr
+    got = [float(v) for v in out.stdout.split()]
+    assert len(got) == len(ts)
+    worst = 0.0
+    for t, v in zip(ts, got):
+        if t == -np.inf or t < -38.5:
+            assert v == 0.0
+            continue
+        if t == np.inf:
+            assert v == 1.0
+            continue
+        ref = mpmath.ncdf(mpmath.mpf(float(t)))
+        if ref < mpmath.mpf("2.2250738585072014e-308"):
+            continue
+        rel = float(abs((mpmath.mpf(v) - ref) / ref))
+        worst = max(worst, rel)
+        assert rel <= 2e-15, (float(t), v, float(ref), rel)
+    print("FP64 normal CDF on the host: max relative error %.2e" % worst)
