@@ -17,7 +17,8 @@
 // coefficients of one sign, so Horner's rule evaluates them without
 // cancellation; the fits' relative error is below 2.1e-16 and the evaluated
 // function stays within a few units in the last place of the exact quantile
-// over p from 1/2 down to the smallest subnormal.
+// over p from 1/2 down to the smallest subnormal; q = 0 and 1 give -inf and
+// +inf, anything outside [0, 1] NaN.
 #pragma once
 
 #include "fp64_math_coeffs.h"
@@ -52,6 +53,7 @@ __host__ __device__ inline double ninv64(double q) {
     const double x = __builtin_fma(-r, r, 0.180625);
     return r * horner64(kNinvCentralP, x) / horner64(kNinvCentralQ, x);
   }
+  if (!(q > 0.0 && q < 1.0)) return q == 0.0 ? -HUGE_VAL : q == 1.0 ? HUGE_VAL : __builtin_nan("");
   const double p = r < 0.0 ? q : 1.0 - q;
   const double s = sqrt(-log(p));
   double z;

@@ -68,6 +68,10 @@ def test_fp64_quantile_against_the_exact_quantile(tmp_path):
         rel = float(abs((mpmath.mpf(z) - ref) / ref))
         worst = max(worst, rel)
         assert rel <= 1e-15, (float(q), z, float(ref), rel)
+    # the interval's ends and values outside it
+    out = subprocess.run([exe], input="0\n1\n-0.5\n1.5\nnan\n", capture_output=True, text=True, timeout=60)
+    ends = [float(v) for v in out.stdout.split()]
+    assert ends[0] == -np.inf and ends[1] == np.inf and all(np.isnan(ends[2:]))
     # the symmetry z(1 - q) = -z(q) holds exactly where 1 - q is exact
     half = qs[qs < 0.5][:200]
     text = "\n".join(repr(float(q)) for q in np.concatenate([half, 1.0 - half])) + "\n"
