@@ -122,6 +122,8 @@ def test_fp64_grid400_full_parity():
 @pytest.mark.parametrize("D,m,N,R,nu,seed", [
     (37, 3, 100, 3, 1.5, 1),      # N not a multiple of 64 (ragged tail of lanes)
     (90, 10, 1, 2, 2.5, 2),       # a single lattice point
+    (70, 15, 100, 3, 1.5, 10),    # 16 variables: the largest terms of the 16-variable set-up tiles
+    (70, 16, 100, 3, 1.5, 11),    # 17 variables: the smallest of the 32-variable tiles
     (64, 31, 200, 2, 0.5, 3),     # the longest unrolled chain
     (80, 32, 130, 2, 1.5, 7),     # the shortest chain of the general kernel
     (120, 50, 300, 3, 1.5, 8),    # m = 50, as in the simulation study
