@@ -53,8 +53,9 @@ __host__ __device__ inline double ninv64(double q) {
     const double x = __builtin_fma(-r, r, 0.180625);
     return r * horner64(kNinvCentralP, x) / horner64(kNinvCentralQ, x);
   }
-  if (!(q > 0.0 && q < 1.0)) return q == 0.0 ? -HUGE_VAL : q == 1.0 ? HUGE_VAL : __builtin_nan("");
+  // outside (0, 1) p is negative or NaN (NaN results) or 0 (infinite results)
   const double p = r < 0.0 ? q : 1.0 - q;
+  if (p == 0.0) return r < 0.0 ? -HUGE_VAL : HUGE_VAL;
   const double s = sqrt(-log(p));
   double z;
   if (s <= 5.0) {
