@@ -23,6 +23,12 @@ relative-error weights, solved in 40-digit arithmetic (mpmath) against
 40-digit targets: from erfinv where p > 1e-8, else from a Newton solve of
 log Phi(z) = log p.
 
+The quantile's tail needs log p. Its logarithm uses the classical reduction
+p = m 2^e, m in [sqrt(1/2), sqrt(2)), log m = 2 atanh(s) with s = (m - 1) / (m + 1),
+|s| <= 3 - 2 sqrt 2; the series' remainder (2 atanh(s) - 2 s) / s = z P(z), z = s^2,
+takes a degree-6 polynomial P fitted here in relative error, and ln 2 is split
+into a head with 42 significant bits (so that e times it is exact) and a tail.
+
 Run: python fit_fp64_math.py   (development-time only; the header is committed)
 """
 from __future__ import annotations
@@ -92,6 +98,24 @@ S2 = mpmath.mpf(5)
 S3 = mpmath.mpf("27.3")
 R2MAX = mpmath.mpf("0.425") ** 2
 
+S_MAX = (mpmath.sqrt(2) - 1) / (mpmath.sqrt(2) + 1)
+
+
+def log_remainder(z):
+    """(2 atanh(s) - 2 s) / (s z), s = sqrt(z): the atanh series after its first term, over z."""
+    if z == 0:
+        return mpmath.mpf(2) / 3
+    s = mpmath.sqrt(z)
+    return (2 * mpmath.atanh(s) - 2 * s) / (s * z)
+
+
+def ln2_split():
+    """ln 2 = hi + lo, hi with 42 significant bits (e * hi exact for |e| < 2^11)."""
+    ln2 = mpmath.log(2)
+    hi = mpmath.floor(ln2 * 2 ** 42) / 2 ** 42
+    return hi, ln2 - hi
+
+
 PIECES = {
     # name: (degrees, variable nodes, target at a node)
     "phi": ((9, 10), lambda: cheb_nodes(0, 38.5, 160), scaled_tail),
@@ -123,6 +147,15 @@ def main():
         out.append(f"constexpr double {pre}Q[{m + 1}] = {{" +
                    ", ".join(mpmath.nstr(c, 20, min_fixed=0, max_fixed=0) for c in q) + "};")
     out.append(f"constexpr double kNinvS1 = {mpmath.nstr(S1, 20)};   // sqrt(-log 0.075)")
+    xs = cheb_nodes(0, S_MAX ** 2, 100)
+    e, p, _ = lawson(xs, [log_remainder(x) for x in xs], 6, 0)
+    print(f"log: degree 6, max relative error of the fit {mpmath.nstr(e, 3)}")
+    out.append(f"// log: the atanh series' remainder over z = s^2, fitted max relative error {mpmath.nstr(e, 3)}")
+    out.append("constexpr double kLogP[7] = {" +
+               ", ".join(mpmath.nstr(c, 20, min_fixed=0, max_fixed=0) for c in p) + "};")
+    hi, lo = ln2_split()
+    out.append(f"constexpr double kLn2Hi = {mpmath.nstr(hi, 20)};   // 42 significant bits")
+    out.append(f"constexpr double kLn2Lo = {mpmath.nstr(lo, 20)};")
     out += ["", "}  // namespace vecchia", ""]
     with open(os.path.join(here, "fp64_math_coeffs.h"), "w") as fh:
         fh.write("\n".join(out))

@@ -1,4 +1,4 @@
-"""The FP64 normal quantile and CDF of the FP64 loops (csrc/device_math_f64.h), built
+"""The FP64 normal quantile, CDF and logarithm of the FP64 loops (csrc/device_math_f64.h), built
 for the host by g++, against the exact quantile computed here with 40-digit
 arithmetic (mpmath): relative error within 1e-15 over q from the smallest
 subnormal to 1 - 2^-53, both sides of 1/2, the pieces' edges included. The
@@ -120,3 +120,42 @@ def test_fp64_normal_cdf_against_the_exact_cdf(tmp_path):
         worst = max(worst, rel)
         assert rel <= 2e-15, (float(t), v, float(ref), rel)
     print("FP64 normal CDF on the host: max relative error %.2e" % worst)
+
+
+def test_fp64_log_against_the_exact_log(tmp_path):
+    # log64 (the quantile's logarithm, device_math_f64.h) on the host against
+    # mpmath's 40-digit log: within one unit in the last place from the smallest
+    # subnormal to the largest double, around 1 and around the reduction's
+    # split at sqrt(1/2); exact at 1
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("g++ not available")
+    exe = str(tmp_path / "log64_check")
+    r = subprocess.run([gxx, "-std=c++17", "-O2", "-mfma", "-I", CSRC,
+                        os.path.join(ROOT, "tests", "host_sanitize", "log64_check.cpp"), "-o", exe],
+                       capture_output=True, text=True)
+    if r.returncode != 0:
+        pytest.skip("host build unavailable: " + r.stderr[-300:])
+    mpmath.mp.dps = 40
+    rng = np.random.default_rng(3)
+    split = 0.70710678118654752
+    xs = np.concatenate([
+        10.0 ** rng.uniform(-323.0, 308.0, 2000),
+        rng.uniform(0.5, 2.0, 1500),
+        1.0 + 10.0 ** rng.uniform(-16.0, -1.0, 400),
+        1.0 - 10.0 ** rng.uniform(-16.0, -1.0, 400),
+        split * (1.0 + rng.uniform(-1e-12, 1e-12, 200)),
+        [5e-324, 1e-310, 2.2250738585072014e-308, 0.5, 2.0, 0.075, 1e308, 1.7976931348623157e308],
+    ])
+    text = "\n".join(repr(float(x)) for x in xs) + "\n"
+    out = subprocess.run([exe], input=text + "1\n", capture_output=True, text=True, timeout=120)
+    assert out.returncode == 0, out.stderr
+    got = [float(v) for v in out.stdout.split()]
+    assert len(got) == len(xs) + 1 and got[-1] == 0.0
+    worst = 0.0
+    for x, v in zip(xs, got):
+        ref = mpmath.log(mpmath.mpf(float(x)))
+        ulps = float(abs(mpmath.mpf(v) - ref)) / np.spacing(abs(float(ref)))
+        worst = max(worst, ulps)
+        assert ulps <= 1.0, (float(x), v, float(ref), ulps)
+    print("FP64 log on the host: max error %.2f units in the last place" % worst)
