@@ -93,6 +93,40 @@ def test_fp64_library_pieces():
     assert err.max() <= 2e-15
 
 
+def test_fp64_quantile_subnormal_and_edge_inputs():
+    # the quantile's own logarithm splits p into mantissa and exponent on the
+    # device (frexp); subnormal p, the smallest normal, 1/2 and the pieces'
+    # edges against the quantile to 40 digits (mpmath, Newton on log Phi)
+    mpmath = pytest.importorskip("mpmath")
+    torch = torch_cuda()
+    from paper_2007_15195_amd import vecchia as V
+    u = np.array([5e-324, 1e-322, 1e-320, 3e-316, 1e-310, 2.2250738585072014e-308, 4.4501477170144028e-308,
+                  1e-300, 1e-100, 1e-20, 0.0749999999, 0.075, 0.0750000001, 0.5, 1.0 - 0.075, 1.0 - 2.0 ** -53])
+    o = _probe(V, torch, V.VECCHIA_PROBE_NINV_F64, u)
+    mpmath.mp.dps = 40
+
+    def exact(q):
+        q = mpmath.mpf(float(q))
+        if q > 0.5:
+            return -exact(1 - q)
+        if q > mpmath.mpf("1e-8"):
+            return -mpmath.sqrt(2) * mpmath.erfinv(1 - 2 * q)
+        z = -mpmath.sqrt(-2 * mpmath.log(q))
+        for _ in range(200):
+            dz = (mpmath.log(mpmath.ncdf(z)) - mpmath.log(q)) / (mpmath.npdf(z) / mpmath.ncdf(z))
+            z -= dz
+            if abs(dz) < mpmath.mpf(10) ** -36:
+                break
+        return z
+
+    for q, z in zip(u, o[:, 0]):
+        ref = exact(q)
+        if ref == 0:
+            assert z == 0.0
+            continue
+        assert abs(float((mpmath.mpf(float(z)) - ref) / ref)) <= 2e-15, (q, z, float(ref))
+
+
 @pytest.mark.parametrize("seed,term,shift,dim,second", [
     (1, 0, 0, 0, False), (0x5EED5EED5EED, 12345, 7, 5, False), (2 ** 64 - 1, 2 ** 31 - 1, 65535, 31, False),
     (77, 3, 2, 32, False), (77, 3, 2, 62, False), (77, 3, 2, 1, True), (9, 2 ** 31 - 1, 65535, 62, True),
