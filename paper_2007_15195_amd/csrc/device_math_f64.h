@@ -20,6 +20,17 @@
 // over p from 1/2 down to the smallest subnormal; q = 0 and 1 give -inf and
 // +inf, anything outside [0, 1] NaN.
 //
+// exp(x), x in [-745, 0] (exp64, the CDF's Gaussian factor): x = k ln 2 + r,
+// |r| <= ln 2 / 2, exp(r) = 1 + r + r^2 g(r) with g fitted in r + 0.3466 >= 0
+// (positive coefficients), scaled by 2^k
+// (a subnormal result below 2^-1022); no range checks, as the CDF's argument
+// is bounded.
+//
+// Quotients of the rationals (div64): their denominators are at least 1 and
+// their numerators moderate, so a reciprocal refined by two Newton steps and
+// one residual correction replaces the IEEE division's scaling and fix-up
+// steps, within about one unit in the last place.
+//
 // log p (log64): p = m 2^e with m in [sqrt(1/2), sqrt(2)); with f = m - 1
 // (exact) and s = f / (2 + f), log m = 2 atanh(s) = f - s f + s R, where
 // R = z P(z), z = s^2, is the series' remainder (P fitted), and f - s f is
@@ -41,14 +52,45 @@ __host__ __device__ __forceinline__ double horner64(const double (&c)[N], double
   return v;
 }
 
+// The same at x >= 0 (up to rounding), evaluated at |x|. On gfx950 an FMA
+// whose operand carries a source modifier keeps the three-operand form, with
+// each coefficient in a pair of scalar registers; without one the compiler
+// prefers the two-operand form and copies every coefficient into vector
+// registers first (two extra vector instructions per coefficient).
+template <int N>
+__host__ __device__ __forceinline__ double horner64_pos(const double (&c)[N], double x) {
+  return horner64(c, __builtin_fabs(x));
+}
+
+// n / d for d >= 1 and a moderate n.
+__host__ __device__ __forceinline__ double div64(double n, double d) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  double r = __builtin_amdgcn_rcp(d);   // about half the bits
+#else
+  double r = 1.0 / d;
+#endif
+  r = __builtin_fma(__builtin_fma(-d, r, 1.0), r, r);
+  r = __builtin_fma(__builtin_fma(-d, r, 1.0), r, r);
+  const double y = n * r;
+  return __builtin_fma(__builtin_fma(-d, y, n), r, y);
+}
+
+// exp(x) for x in [-745, 0].
+__host__ __device__ __forceinline__ double exp64(double x) {
+  const double k = __builtin_rint(x * 1.44269504088896340736);   // x / ln 2, to the nearest integer
+  const double r = __builtin_fma(-k, kLn2Lo, __builtin_fma(-k, kLn2Hi, x));
+  const double e = 1.0 + __builtin_fma(r * r, horner64_pos(kExpG, r + kExpShift), r);
+  return __builtin_ldexp(e, (int)k);
+}
+
 __host__ __device__ inline double phi64(double t) {
   const double a = __builtin_fabs(t);
   double lower = 0.0;   // Phi(-a)
   if (a <= 38.5) {
-    const double R = horner64(kPhiRP, a) / horner64(kPhiRQ, a);
+    const double R = div64(horner64(kPhiRP, a), horner64(kPhiRQ, a));
     const double h = a * a;
     const double l = __builtin_fma(a, a, -h);   // h + l = a^2 exactly
-    lower = R * (exp(-0.5 * h) * (1.0 - 0.5 * l));
+    lower = R * (exp64(-0.5 * h) * (1.0 - 0.5 * l));
   } else if (!(a > 38.5)) {
     return t;   // NaN
   }
@@ -64,9 +106,9 @@ __host__ __device__ __forceinline__ double log64(double x) {
     --e;
   }
   const double f = m - 1.0;
-  const double s = f / (2.0 + f);
+  const double s = div64(f, 2.0 + f);
   const double z = s * s;
-  const double R = z * horner64(kLogP, z);
+  const double R = z * horner64_pos(kLogP, z);
   const double hf = 0.5 * f * f;
   const double de = (double)e;
   return de * kLn2Hi + (f - (hf - (s * (hf + R) + de * kLn2Lo)));
@@ -76,7 +118,7 @@ __host__ __device__ inline double ninv64(double q) {
   const double r = q - 0.5;
   if (__builtin_fabs(r) <= 0.425) {
     const double x = __builtin_fma(-r, r, 0.180625);
-    return r * horner64(kNinvCentralP, x) / horner64(kNinvCentralQ, x);
+    return r * div64(horner64_pos(kNinvCentralP, x), horner64_pos(kNinvCentralQ, x));
   }
   // outside (0, 1) p is negative or NaN (NaN results) or 0 (infinite results)
   const double p = r < 0.0 ? q : 1.0 - q;
@@ -85,10 +127,10 @@ __host__ __device__ inline double ninv64(double q) {
   double z;
   if (s <= 5.0) {
     const double x = s - kNinvS1;
-    z = horner64(kNinvTail1P, x) / horner64(kNinvTail1Q, x);
+    z = div64(horner64_pos(kNinvTail1P, x), horner64_pos(kNinvTail1Q, x));
   } else {
     const double x = s - 5.0;
-    z = horner64(kNinvTail2P, x) / horner64(kNinvTail2Q, x);
+    z = div64(horner64_pos(kNinvTail2P, x), horner64_pos(kNinvTail2Q, x));
   }
   return r < 0.0 ? -z : z;
 }

@@ -23,6 +23,12 @@ relative-error weights, solved in 40-digit arithmetic (mpmath) against
 40-digit targets: from erfinv where p > 1e-8, else from a Newton solve of
 log Phi(z) = log p.
 
+The CDF's Gaussian factor needs exp(x) for x in [-745, 0]: x = k ln 2 + r with
+|r| <= ln 2 / 2 (ln 2 in the same two parts as below), exp(r) = 1 + r + r^2 g(r),
+g a degree-10 polynomial in u = r + 0.3466 >= 0 fitted here in relative error
+(g is absolutely monotone, so its coefficients in u are positive), and the
+result 2^k exp(r).
+
 The quantile's tail needs log p. Its logarithm uses the classical reduction
 p = m 2^e, m in [sqrt(1/2), sqrt(2)), log m = 2 atanh(s) with s = (m - 1) / (m + 1),
 |s| <= 3 - 2 sqrt 2; the series' remainder (2 atanh(s) - 2 s) / s = z P(z), z = s^2,
@@ -109,6 +115,16 @@ def log_remainder(z):
     return (2 * mpmath.atanh(s) - 2 * s) / (s * z)
 
 
+EXP_SHIFT = mpmath.mpf("0.3466")
+
+
+def exp_remainder(r):
+    """(exp(r) - 1 - r) / r^2, 40 digits."""
+    if r == 0:
+        return mpmath.mpf(1) / 2
+    return (mpmath.exp(r) - 1 - r) / (r * r)
+
+
 def ln2_split():
     """ln 2 = hi + lo, hi with 42 significant bits (e * hi exact for |e| < 2^11)."""
     ln2 = mpmath.log(2)
@@ -152,6 +168,14 @@ def main():
     print(f"log: degree 6, max relative error of the fit {mpmath.nstr(e, 3)}")
     out.append(f"// log: the atanh series' remainder over z = s^2, fitted max relative error {mpmath.nstr(e, 3)}")
     out.append("constexpr double kLogP[7] = {" +
+               ", ".join(mpmath.nstr(c, 20, min_fixed=0, max_fixed=0) for c in p) + "};")
+    xs = cheb_nodes(0, 2 * EXP_SHIFT, 120)
+    e, p, _ = lawson(xs, [exp_remainder(x - EXP_SHIFT) for x in xs], 10, 0)
+    print(f"exp: degree 10, max relative error of the fit {mpmath.nstr(e, 3)}")
+    out.append(f"// exp: (exp(r) - 1 - r) / r^2 in u = r + kExpShift on |r| <= kExpShift, "
+               f"fitted max relative error {mpmath.nstr(e, 3)}")
+    out.append(f"constexpr double kExpShift = {mpmath.nstr(EXP_SHIFT, 20)};")
+    out.append("constexpr double kExpG[11] = {" +
                ", ".join(mpmath.nstr(c, 20, min_fixed=0, max_fixed=0) for c in p) + "};")
     hi, lo = ln2_split()
     out.append(f"constexpr double kLn2Hi = {mpmath.nstr(hi, 20)};   // 42 significant bits")

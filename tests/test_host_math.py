@@ -1,4 +1,4 @@
-"""The FP64 normal quantile, CDF and logarithm of the FP64 loops (csrc/device_math_f64.h), built
+"""The FP64 normal quantile and CDF of the FP64 loops and their logarithm and exponential (csrc/device_math_f64.h), built
 for the host by g++, against the exact quantile computed here with 40-digit
 arithmetic (mpmath): relative error within 1e-15 over q from the smallest
 subnormal to 1 - 2^-53, both sides of 1/2, the pieces' edges included. The
@@ -159,3 +159,38 @@ def test_fp64_log_against_the_exact_log(tmp_path):
         worst = max(worst, ulps)
         assert ulps <= 1.0, (float(x), v, float(ref), ulps)
     print("FP64 log on the host: max error %.2f units in the last place" % worst)
+
+
+def test_fp64_exp_against_the_exact_exp(tmp_path):
+    # exp64 (the normal CDF's Gaussian factor, device_math_f64.h) on the host
+    # against mpmath's 40-digit exp over its domain [-745, 0]: within one unit in
+    # the last place (one subnormal step where the result is subnormal); exact at 0
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("g++ not available")
+    exe = str(tmp_path / "exp64_check")
+    r = subprocess.run([gxx, "-std=c++17", "-O2", "-mfma", "-I", CSRC,
+                        os.path.join(ROOT, "tests", "host_sanitize", "exp64_check.cpp"), "-o", exe],
+                       capture_output=True, text=True)
+    if r.returncode != 0:
+        pytest.skip("host build unavailable: " + r.stderr[-300:])
+    mpmath.mp.dps = 40
+    rng = np.random.default_rng(5)
+    ln2h = 0.34657359027997264
+    xs = np.concatenate([
+        rng.uniform(-745.0, 0.0, 3000),
+        -(10.0 ** rng.uniform(-20.0, 2.8, 1500)),
+        [-745.0, -744.4, -708.4, -708.39, -ln2h, -ln2h * (1 + 1e-15), -ln2h * 3, -1e-300],
+    ])
+    text = "\n".join(repr(float(x)) for x in xs) + "\n"
+    out = subprocess.run([exe], input=text + "0\n", capture_output=True, text=True, timeout=120)
+    assert out.returncode == 0, out.stderr
+    got = [float(v) for v in out.stdout.split()]
+    assert len(got) == len(xs) + 1 and got[-1] == 1.0
+    worst = 0.0
+    for x, v in zip(xs, got):
+        ref = mpmath.exp(mpmath.mpf(float(x)))
+        ulps = float(abs(mpmath.mpf(v) - ref)) / np.spacing(float(ref))
+        worst = max(worst, ulps)
+        assert ulps <= 1.0, (float(x), v, float(ref), ulps)
+    print("FP64 exp on the host: max error %.2f units in the last place" % worst)
