@@ -51,6 +51,19 @@ __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirs
 // scalar, so the result is wave-uniform)
 __device__ __forceinline__ bool any_lane(bool p) { return __builtin_amdgcn_ballot_w64(p) != 0; }
 
+// The work item of this block. Consecutive blocks go to the chip's 8 XCDs in
+// turn (block b to XCD b mod 8), each with its own L2; the blocks of one XCD
+// take one contiguous range of the launch's items instead, so that the items
+// of one term (consecutive) share an L2 for the term's rows and for the lines
+// of their partial sums. A bijection of [0, gridDim.x) for any grid size; the
+// results do not depend on it.
+constexpr unsigned kXcds = 8;
+__device__ __forceinline__ int64_t block_item(int64_t item_base) {
+  const unsigned b = blockIdx.x, n = gridDim.x;
+  const unsigned x = b % kXcds, j = b / kXcds, q = n / kXcds, r = n % kXcds;
+  return item_base + (int64_t)(x * q + (x < r ? x : r) + j);
+}
+
 struct Item {
   const InstDesc* I;
   int64_t i;      // plan index of the term
@@ -496,7 +509,7 @@ __global__ __launch_bounds__(64) void qmc_gen_f32(const InstDesc* __restrict__ i
                                                   const RangeDesc* __restrict__ ranges, int n_ranges,
                                                   const Aux32* __restrict__ aux32, const uint64_t* __restrict__ Zg,
                                                   double* __restrict__ sums, int64_t item_base) {
-  const Item it = decode_item(insts, ranges, n_ranges, item_base + (int64_t)blockIdx.x);
+  const Item it = decode_item(insts, ranges, n_ranges, block_item(item_base));
   item_f32_gen(it, aux32, Zg, sums);
 }
 
@@ -504,7 +517,7 @@ __global__ __launch_bounds__(64) void qmc_gen_f64(const InstDesc* __restrict__ i
                                                   const RangeDesc* __restrict__ ranges, int n_ranges,
                                                   const Aux64* __restrict__ aux64, const uint64_t* __restrict__ Zg,
                                                   double* __restrict__ sums, int64_t item_base) {
-  const Item it = decode_item(insts, ranges, n_ranges, item_base + (int64_t)blockIdx.x);
+  const Item it = decode_item(insts, ranges, n_ranges, block_item(item_base));
   item_f64_gen(it, aux64, Zg, sums, reinterpret_cast<const double*>(it.I->prep) + it.i * it.I->prep_stride);
 }
 
@@ -585,7 +598,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(f64_min_wave
     const InstDesc* __restrict__ insts, const RangeDesc* __restrict__ ranges, int n_ranges,
     const Aux64* __restrict__ aux64, const uint64_t* __restrict__ Zg, double* __restrict__ sums,
     int64_t item_base) {
-  const Item it = decode_item(insts, ranges, n_ranges, item_base + (int64_t)blockIdx.x);
+  const Item it = decode_item(insts, ranges, n_ranges, block_item(item_base));
   item_f64<K, BLOCK>(it, aux64, Zg, sums);
 }
 
@@ -597,7 +610,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(f32_min_wave
                                               const Aux32* __restrict__ aux32,
                                               const uint64_t* __restrict__ Zg, double* __restrict__ sums,
                                               int64_t item_base) {
-  const Item it = decode_item(insts, ranges, n_ranges, item_base + (int64_t)blockIdx.x);
+  const Item it = decode_item(insts, ranges, n_ranges, block_item(item_base));
   item_f32<K, BLOCK>(it, aux32, Zg, sums);
 }
 
